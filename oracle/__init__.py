@@ -1,0 +1,151 @@
+"""FP64 CPU oracle for kinetic maximum-principle bounds and the squeeze limiter.
+
+TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+baseline leg of the bench import this package.  It wraps ``liboracle.so``
+(built from ``kbl_oracle.c`` with gcc, FP64, no fast-math) through ctypes and
+shares no code with the HIP library.
+
+Functions take NumPy arrays and the plain workload fields; see
+``kbl_oracle.c`` for the passages of the paper each step follows.
+
+Parity status: bounds and limiter are pinned by the closed-form, printed-value,
+invariant and brute-force checks in ``tests/test_oracle_*.py``.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "kbl_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+ST_INADMISSIBLE = 0x1
+ST_RHO_FLOOR = 0x2
+ST_EPS_RULE = 0x4
+ST_LIMITED = 0x8
+ST_PSTEP = 0x10
+ST_PMEAN_FLOOR = 0x20
+ST_MEAN_OUTSIDE = 0x40
+ST_BAD_BOUNDS = 0x80
+
+RHO_FLOOR = 1e-12     # Sec. 3.8
+P_FLOOR = 1e-12       # Sec. 3.8
+EPS_ALPHA = 1e-13     # Sec. 3.4
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with gcc (-O2 -fopenmp, strict IEEE)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+               "-D_DEFAULT_SOURCE", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        P = C.c_void_p
+        lib.oracle_bounds.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
+                                      C.c_int, P, P, P, C.c_double,
+                                      C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P]
+        lib.oracle_bounds.restype = C.c_int
+        lib.oracle_limit.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
+                                     C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P, P]
+        lib.oracle_limit.restype = C.c_int
+        lib.oracle_delta.argtypes = [C.c_int, C.c_double]
+        lib.oracle_delta.restype = C.c_double
+        _lib = lib
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
+           cols: np.ndarray, n_s: int, grid_mode: int, n, lo=(0.0, 0.0),
+           hi=(0.0, 0.0), k: float = 4.0, r_fac: float = 1e-3,
+           rho_floor: float = RHO_FLOOR,
+           elems: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Kinetic bounds [2(d+2), n_sel] and status [n_sel] (Sec. 3.3-3.8)."""
+    lib = _load()
+    states = np.ascontiguousarray(states, dtype=np.float64)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    n_elem = rowptr.size - 1
+    assert states.shape == (dim + 2, n_elem * n_s)
+    if elems is not None:
+        elems = np.ascontiguousarray(elems, dtype=np.int64)
+        n_sel = elems.size
+    else:
+        n_sel = n_elem
+    n_arr = np.array(list(n) + [2] * (2 - len(n)), dtype=np.int32)[:2]
+    lo_arr = np.array(list(lo) + [0.0] * (2 - len(lo)), dtype=np.float64)[:2]
+    hi_arr = np.array(list(hi) + [0.0] * (2 - len(hi)), dtype=np.float64)[:2]
+    out = np.empty((2 * (dim + 2), n_sel), dtype=np.float64)
+    st = np.empty(n_sel, dtype=np.uint32)
+    rc = lib.oracle_bounds(dim, gamma, r_fac, rho_floor, grid_mode, _p(n_arr), _p(lo_arr),
+                           _p(hi_arr), k, n_elem, n_s, _p(states), _p(rowptr), _p(cols),
+                           _p(elems), n_sel, _p(out), _p(st))
+    if rc != 0:
+        raise ValueError("oracle_bounds rejected its arguments")
+    return out, st
+
+
+def limit(dim: int, gamma: float, solution: np.ndarray, bounds_sel: np.ndarray,
+          node_weights: np.ndarray, n_s: int, p_floor: float = P_FLOOR,
+          eps: float = EPS_ALPHA, elems: Optional[np.ndarray] = None):
+    """Squeeze limiter + pressure step (Sec. 3.4, 3.8).
+
+    Returns (limited [d+2, n_sel*n_s], alpha [2, n_sel], status [n_sel]).
+    ``bounds_sel`` holds one column per selected element.
+    """
+    lib = _load()
+    solution = np.ascontiguousarray(solution, dtype=np.float64)
+    bounds_sel = np.ascontiguousarray(bounds_sel, dtype=np.float64)
+    c = np.ascontiguousarray(node_weights, dtype=np.float64)
+    n_elem = solution.shape[1] // n_s
+    if elems is not None:
+        elems = np.ascontiguousarray(elems, dtype=np.int64)
+        n_sel = elems.size
+    else:
+        n_sel = n_elem
+    assert bounds_sel.shape == (2 * (dim + 2), n_sel)
+    lim = np.empty((dim + 2, n_sel * n_s), dtype=np.float64)
+    al = np.empty((2, n_sel), dtype=np.float64)
+    st = np.empty(n_sel, dtype=np.uint32)
+    rc = lib.oracle_limit(dim, gamma, p_floor, eps, n_elem, n_s, _p(solution), _p(bounds_sel),
+                          _p(c), _p(elems), n_sel, _p(lim), _p(al), _p(st))
+    if rc != 0:
+        raise ValueError("oracle_limit rejected its arguments")
+    return lim, al, st
+
+
+def delta(dim: int, gamma: float) -> float:
+    return _load().oracle_delta(dim, gamma)
+
+
+def workload_bounds(wl, elems=None, r_fac=None):
+    """Convenience: bounds of a synth.Workload (or a selection of its elements)."""
+    g = wl.grid
+    return bounds(wl.dim, wl.gamma, wl.states, wl.rowptr, wl.cols, wl.n_s, g.mode,
+                  g.n[: wl.dim], g.lo, g.hi, g.k, wl.r_fac if r_fac is None else r_fac,
+                  elems=elems)
+
+
+def workload_limit(wl, bounds_sel, elems=None):
+    return limit(wl.dim, wl.gamma, wl.target, bounds_sel, wl.node_weights, wl.n_s, elems=elems)
