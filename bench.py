@@ -1,0 +1,175 @@
+"""Throughput of the kinetic bounds + limiter hot path on one MI355X.
+
+    python bench.py [--steps K] [--warmup W] [--workload quad256] [--no-cpu-baseline]
+
+One step = kbl_compute_bounds + kbl_limit over the whole workload, inputs
+already resident in HBM.  Prints ONE JSON line (rank 0) with the throughput
+in elements/s, the roofline of the dominant kernel (the bounds pass, bound by
+VALU issue) measured with HIP events on the launch stream, and the FP64 CPU
+oracle timed on a bounded element sample on the host cores.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X: 256 CUs, 2.4 GHz peak engine clock, 64 VALU lanes per CU per clock
+# for FP64 (and unpacked FP32) add/min/max.  One lane-op per clock per lane.
+N_CU = 256
+CLOCK_HZ = 2.4e9
+LANES_PER_CU = 64
+VALU_PEAK_OPS = N_CU * CLOCK_HZ * LANES_PER_CU          # 3.93e13 lane-ops/s
+HBM_PEAK = 8.0e12
+
+METRIC = "element-bounds+limit/s at stated tol, FP64 vs mixed; % VALU/MFMA roofline"
+
+WORKLOAD_TEXT = {
+    "quad256": ("2D Euler gamma=1.4, 256x256 periodic quads, p=3 (4x4 Gauss-Legendre nodes), "
+                "5-element face stencils (80 states), 48x48 per-stencil velocity grid (k=4), "
+                "r_fac=1e-3, 4-quadrant Riemann field rho in [0.1,10], p in [0.1,100], |U|<=3 "
+                "+1% smooth perturbation"),
+    "quad1024_sine": ("2D Euler gamma=1.4, 1024x1024 periodic quads, p=3, 80-state stencils, "
+                      "64x64 global velocity grid on [-12,12]^2 sqrt(theta_max), sine + Sod-jump field"),
+    "tri2m": ("2D Euler gamma=1.4, 2,000,000 jittered P2 triangles (6 nodes), vertex-neighbour "
+              "stencils (4-16 elements), 64x64 per-stencil velocity grid (k=4), radial shock "
+              "rho ratio 1e3, p ratio 1e5"),
+    "quad512": ("2D Euler gamma=1.4, 512x512 periodic quads, p=3, 80-state stencils, 48x48 "
+                "per-stencil velocity grid (k=4), 4-quadrant Riemann field"),
+    "line64": ("1D Euler gamma=1.4, 64 elements, p=3, 12-state stencils, 64-node global velocity "
+               "grid on [-12,12] sqrt(theta_max), sine + Sod jump"),
+}
+
+
+def pair_ops(dim: int) -> int:
+    """Algorithmic VALU lane-ops per (stencil state, velocity node) pair.
+
+    2D: the log-Maxwellian is separable, q = A[jx] + B[jy]: two adds (q and
+    q + ln(theta delta/2)) and four running min/max.  1D: sub, mul, fma, fma,
+    then four min/max.
+    """
+    return 6 if dim == 2 else 8
+
+
+def cpu_baseline(wl, target_s: float = 12.0):
+    import oracle
+    oracle.build(force=False)
+    rng = np.random.default_rng(12345)
+    # calibrate on a small sample, then run ~target_s of wall time
+    probe = np.sort(rng.choice(wl.n_elem, min(32, wl.n_elem), replace=False))
+    t0 = time.perf_counter()
+    rb, _ = oracle.workload_bounds(wl, elems=probe)
+    oracle.workload_limit(wl, rb, elems=probe)
+    dt = time.perf_counter() - t0
+    n = int(min(wl.n_elem, max(64, len(probe) * target_s / max(dt, 1e-6))))
+    sample = np.sort(rng.choice(wl.n_elem, n, replace=False))
+    t0 = time.perf_counter()
+    rb, _ = oracle.workload_bounds(wl, elems=sample)
+    oracle.workload_limit(wl, rb, elems=sample)
+    dt = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    return {"value": n / dt, "unit": "elements/s", "cores": cores, "kind": "oracle",
+            "sample": f"{n} seeded random elements of the same workload (bounds + limit), "
+                      f"{dt:.1f} s wall, FP64 direct-form oracle (gcc -O2, OpenMP)"}
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="quad256")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs the bounds path on a single "
+              "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2407_20966_amd as kbl
+    import synth
+
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    wl = synth.make_workload(args.workload)
+    g = wl.grid
+    st = torch.from_numpy(wl.states).to(dev)
+    rp = torch.from_numpy(wl.rowptr).to(dev)
+    cl = torch.from_numpy(wl.cols).to(dev)
+    tg = torch.from_numpy(wl.target).to(dev)
+    vg = kbl.make_vgrid(g.mode, g.n[: wl.dim], g.lo, g.hi, g.k)
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    bounds = torch.empty((2 * (wl.dim + 2), wl.n_elem), dtype=torch.float64, device=dev)
+    bstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+    lim = torch.empty_like(tg)
+    alpha = torch.empty((2, wl.n_elem), dtype=torch.float64, device=dev)
+    lstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm, out=bounds, status=bstat, stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        kbl.limit(tg, bounds, wl.node_weights, wl.n_s, prm, out=lim, alpha=alpha, status=lstat,
+                  stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = 1e3 * wall / args.steps
+    b_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    l_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    print(f"[bench] {ms_step:.3f} ms/step (bounds {b_ms:.3f} ms, limit {l_ms:.3f} ms)",
+          file=sys.stderr, flush=True)
+
+    pairs = wl.pairs()
+    ops = pairs * pair_ops(wl.dim)
+    achieved = ops / (b_ms * 1e-3)
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
+            "kernel": "bounds_fp64_2d" if wl.dim == 2 else "bounds_fp64_1d",
+            "ops_per_launch": ops, "pairs_per_launch": pairs,
+            "ops_per_pair": pair_ops(wl.dim), "kernel_ms": b_ms, "limit_ms": l_ms,
+            "limit_hbm_frac": (2 * wl.target.nbytes + bounds.numel() * 8 + alpha.numel() * 8
+                               + lstat.numel() * 4) / (l_ms * 1e-3) / HBM_PEAK}
+    out = {"metric": METRIC, "value": wl.n_elem / (ms_step * 1e-3), "unit": "elements/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic",
+           "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, '')}",
+                      "n_elem": wl.n_elem, "nodes_per_elem": wl.n_s,
+                      "velocity_grid": list(g.n[: wl.dim]), "precision": "fp64",
+                      "parity_tol": 1e-12},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(wl)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

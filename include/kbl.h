@@ -1,0 +1,154 @@
+/*
+ * kbl.h - kinetic maximum-principle bounds and squeeze limiting for the Euler
+ * equations on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Dzanic & Martinelli, "High-order limiting methods using maximum
+ * principle bounds derived from the Boltzmann equation I: Euler equations".
+ * For every element, the Maxwellian of each state in the element's stencil is
+ * evaluated on a discrete velocity grid (Sec. 2.2, eq. maxwell), the pointwise
+ * min/max distribution is taken (Sec. 3.2-3.3, eq. fminmax; relaxed per
+ * Sec. 3.5), its moments give bounds on density, momentum and total energy
+ * (eq. rhobounds, Ebounds, mmbounds, mpbounds; internal energy per Sec. 3.6;
+ * trapezoid quadrature per Sec. 3.7), and the coupled squeeze limiter pulls
+ * the element's nodal solution into those bounds (Sec. 3.4, eq. alpha,
+ * eq. limiter) followed by the pressure step of Sec. 3.8.
+ *
+ * Conventions for every entry point
+ *  - Array pointers are DEVICE pointers owned by the caller unless stated
+ *    otherwise.  The library allocates nothing and keeps no device memory
+ *    between calls.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Work is enqueued
+ *    on it and the call returns without synchronising.
+ *  - Argument errors are detected on the host before any launch and returned
+ *    synchronously (nothing is enqueued).  A launch failure returns
+ *    KBL_ERR_HIP.  Data-dependent conditions never fail a call: they are
+ *    reported per element in `elem_status` bits (see KBL_ST_*).
+ *  - Conserved states are stored SoA: row v of a [d+2][n_elem*n_s] array
+ *    holds variable v (rho, m_1..m_d, E) of every node; the nodes of element e
+ *    are e*n_s .. e*n_s+n_s-1.
+ *  - Spatial dimension d is 1 or 2.  gamma > 1 and delta = 2/(gamma-1) - d
+ *    must be >= 0 (Sec. 3.6).
+ *  - No exception crosses this interface.
+ */
+#ifndef KBL_H
+#define KBL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    KBL_OK = 0,
+    KBL_ERR_ARG = 1,          /* bad dimension, size, pointer or parameter */
+    KBL_ERR_GAMMA = 2,        /* gamma <= 1 or delta = 2/(gamma-1) - d < 0 */
+    KBL_ERR_GRID = 3,         /* velocity grid: n < 2, hi <= lo, k <= 0 or too many nodes */
+    KBL_ERR_UNSUPPORTED = 4,  /* combination not built (see kbl_status_string) */
+    KBL_ERR_HIP = 5,          /* a HIP runtime call or launch failed */
+    KBL_ERR_WORKSPACE = 6     /* workspace missing or too small */
+} kbl_status;
+
+/* Velocity-grid modes (Sec. 3.7). */
+#define KBL_GRID_GLOBAL  0    /* one box [lo, hi] for every element */
+#define KBL_GRID_STENCIL 1    /* per element: [min_S(U - k sqrt(theta)), max_S(U + k sqrt(theta))] */
+
+/* Arithmetic of the bounds pass. */
+#define KBL_PREC_FP64        0   /* every step in FP64 */
+#define KBL_PREC_MIXED_BF16  1   /* FP32 envelopes/exp, BF16 MFMA contraction (hi/lo split) */
+#define KBL_PREC_MIXED_FP16  2   /* FP32 envelopes/exp, FP16 MFMA contraction (hi/lo split) */
+
+/* Per-element status bits.  kbl_compute_bounds writes bits 0x1-0x2 and 0x100;
+ * kbl_limit writes bits 0x4-0x80. */
+#define KBL_ST_INADMISSIBLE  0x1u    /* a stencil state has rho<=0, P<=0 or a non-finite value: bounds are NaN */
+#define KBL_ST_RHO_FLOOR     0x2u    /* rho_min was raised to rho_floor (Sec. 3.8) */
+#define KBL_ST_EPS_RULE      0x4u    /* some alpha_i was set to 0 by the epsilon rule (Sec. 3.4) */
+#define KBL_ST_LIMITED       0x8u    /* alpha_min < 1 */
+#define KBL_ST_PSTEP         0x10u   /* the pressure step fired (Sec. 3.8) */
+#define KBL_ST_PMEAN_FLOOR   0x20u   /* P(mean) <= p_floor: alpha_P = 0 (element flattened) */
+#define KBL_ST_MEAN_OUTSIDE  0x40u   /* element mean lies outside its bounds */
+#define KBL_ST_BAD_BOUNDS    0x80u   /* bounds not finite: element passed through unchanged */
+#define KBL_ST_BAD_STENCIL   0x100u  /* stencil row out of range (rowptr or cols): bounds are NaN */
+
+typedef struct {
+    int32_t mode;       /* KBL_GRID_GLOBAL or KBL_GRID_STENCIL */
+    int32_t n[2];       /* nodes per direction, endpoints included (n[1] ignored for d = 1) */
+    double  lo[2];      /* GLOBAL: lower box corner */
+    double  hi[2];      /* GLOBAL: upper box corner */
+    double  k;          /* STENCIL: extent in thermal units (the paper uses 4 in 2D, 8 in 1D) */
+} kbl_vgrid;
+
+typedef struct {
+    double  gamma;      /* ratio of specific heats */
+    double  r_fac;      /* relaxation factor, 0 <= r_fac < 1 (Sec. 3.5; the paper uses 1e-3) */
+    double  rho_floor;  /* density floor on rho_min (Sec. 3.8; 1e-12) */
+    double  p_floor;    /* pressure floor of the pressure step (Sec. 3.8; 1e-12) */
+    double  eps_alpha;  /* epsilon of the limiter's degenerate-range rule (Sec. 3.4; 1e-13) */
+    int32_t precision;  /* KBL_PREC_* (kbl_compute_bounds only) */
+    int32_t reserved;   /* must be 0 */
+} kbl_params;
+
+/* Fills `p` with the paper's defaults for the given gamma (r_fac 1e-3, floors
+ * 1e-12, epsilon 1e-13, FP64). */
+void kbl_default_params(kbl_params* p, double gamma);
+
+/*
+ * kbl_compute_bounds - kinetic local-maximum-principle bounds per element.
+ * Follows steps 1-3 of the overview in Sec. 3.9: collect the stencil states,
+ * evaluate f_min/f_max (eq. fminmax, eq. relaxed) on the velocity grid of
+ * Sec. 3.7 with the internal-energy model of Sec. 3.6, integrate the moments
+ * (eq. rhobounds, Ebounds, mmbounds, mpbounds) and floor rho_min (Sec. 3.8).
+ *
+ *   states       [d+2][n_elem*n_s] FP64 conserved states of every node.
+ *   rowptr, cols element stencil in CSR form: row e lists element ids
+ *                (self included by the caller); every node of every listed
+ *                element is a stencil state.  rowptr has n_elem+1 entries,
+ *                cols has nnz entries.  Rows that leave [0, nnz] or name an
+ *                element outside [0, n_elem) get KBL_ST_BAD_STENCIL and NaN
+ *                bounds; nothing outside the two arrays is read.
+ *   vgrid        host pointer, copied during the call.
+ *   bounds       out [2(d+2)][n_elem] FP64: rows (rho, m_1..m_d, E)_min then
+ *                (rho, m_1..m_d, E)_max.
+ *   elem_status  out [n_elem] or NULL.
+ * Precision KBL_PREC_MIXED_* computes the envelopes in FP32 and the moment
+ * contraction on MFMA; the velocity box, exp scaling and floors stay FP64.
+ */
+kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_elem,
+                              int32_t n_s, int64_t nnz, const double* states,
+                              const int32_t* rowptr, const int32_t* cols,
+                              const kbl_vgrid* vgrid, double* bounds,
+                              uint32_t* elem_status, void* stream);
+
+/*
+ * kbl_limit - coupled squeeze limiter (Sec. 3.4, eq. alpha and eq. limiter,
+ * with the epsilon rule) and pressure step (Sec. 3.8, eq. pmin and
+ * eq. doublelimit), all in FP64.  Steps 5-7 of the overview in Sec. 3.9.
+ *
+ *   solution     [d+2][n_elem*n_s] nodal solution to limit.
+ *   bounds       [2(d+2)][n_elem] as written by kbl_compute_bounds.
+ *   node_weights HOST pointer, n_s positive weights c_j of the element mean
+ *                (Assumption (iii)(a) of Sec. 4); copied during the call.
+ *   limited      out [d+2][n_elem*n_s]; may alias `solution`.
+ *   alpha        out [2][n_elem] (alpha_min, alpha_P; alpha_P = 1 when the
+ *                pressure step does not fire) or NULL.
+ *   elem_status  out [n_elem] or NULL.
+ * n_s must be at most 64.  When P(mean) <= p_floor the pressure step uses
+ * alpha_P = 0.  Non-finite bounds leave the element unchanged.
+ */
+kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
+                     const double* solution, const double* bounds,
+                     const double* node_weights, double* limited, double* alpha,
+                     uint32_t* elem_status, void* stream);
+
+/* Human-readable text for a status code (static storage). */
+const char* kbl_status_string(kbl_status s);
+
+/* Library version as 10000*major + 100*minor + patch. */
+int32_t kbl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KBL_H */

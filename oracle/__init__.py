@@ -33,6 +33,7 @@ ST_PSTEP = 0x10
 ST_PMEAN_FLOOR = 0x20
 ST_MEAN_OUTSIDE = 0x40
 ST_BAD_BOUNDS = 0x80
+ST_BAD_STENCIL = 0x100
 
 RHO_FLOOR = 1e-12     # Sec. 3.8
 P_FLOOR = 1e-12       # Sec. 3.8
@@ -61,7 +62,7 @@ def _load():
         P = C.c_void_p
         lib.oracle_bounds.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_int, P, P, P, C.c_double,
-                                      C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P]
+                                      C.c_int64, C.c_int, C.c_int64, P, P, P, P, C.c_int64, P, P]
         lib.oracle_bounds.restype = C.c_int
         lib.oracle_limit.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                      C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P, P]
@@ -99,7 +100,7 @@ def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
     out = np.empty((2 * (dim + 2), n_sel), dtype=np.float64)
     st = np.empty(n_sel, dtype=np.uint32)
     rc = lib.oracle_bounds(dim, gamma, r_fac, rho_floor, grid_mode, _p(n_arr), _p(lo_arr),
-                           _p(hi_arr), k, n_elem, n_s, _p(states), _p(rowptr), _p(cols),
+                           _p(hi_arr), k, n_elem, n_s, cols.size, _p(states), _p(rowptr), _p(cols),
                            _p(elems), n_sel, _p(out), _p(st))
     if rc != 0:
         raise ValueError("oracle_bounds rejected its arguments")

@@ -41,6 +41,7 @@
 #define OR_ST_PMEAN_FLOOR  0x20u  /* P(mean) <= pressure floor, alpha_P set to 0 */
 #define OR_ST_MEAN_OUTSIDE 0x40u  /* element mean lies outside the bounds */
 #define OR_ST_BAD_BOUNDS   0x80u  /* bounds not finite: element passed through */
+#define OR_ST_BAD_STENCIL  0x100u /* stencil row empty or out of range: bounds are NaN */
 
 #define OR_MAXV 4                 /* d+2 for d<=2 */
 
@@ -103,13 +104,22 @@ static double maxwellian(int d, const prim_t* s, const double* u) {
 static unsigned element_bounds(int d, double gamma, double r_fac, double rho_floor,
                                int grid_mode, const int* n, const double* lo_in,
                                const double* hi_in, double k, int n_s,
-                               const double* states, int64_t n_nodes,
+                               const double* states, int64_t n_elem, int64_t nnz,
                                const int* rowptr, const int* cols, int64_t e,
                                double* out) {
     const int nv = d + 2;
+    const int64_t n_nodes = n_elem * n_s;
     const int row0 = rowptr[e], row1 = rowptr[e + 1];
+    /* a row must be non-empty, inside [0, nnz] and name existing elements */
+    int bad_row = (row0 < 0 || row1 <= row0 || row1 > nnz);
+    for (int r = row0; !bad_row && r < row1; ++r)
+        if (cols[r] < 0 || cols[r] >= n_elem) bad_row = 1;
+    if (bad_row) {
+        for (int v = 0; v < 2 * nv; ++v) out[v] = NAN;
+        return OR_ST_BAD_STENCIL;
+    }
     const int S = (row1 - row0) * n_s;
-    prim_t* st = (prim_t*)malloc(sizeof(prim_t) * (size_t)(S > 0 ? S : 1));
+    prim_t* st = (prim_t*)malloc(sizeof(prim_t) * (size_t)S);
     unsigned status = 0;
 
     /* Step 1 of Sec. 3.9: collect the stencil states (CSR order, node order). */
@@ -120,10 +130,10 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
             if (!st[s].ok) status |= OR_ST_INADMISSIBLE;
             ++s;
         }
-    if (status & OR_ST_INADMISSIBLE || S == 0) {
+    if (status & OR_ST_INADMISSIBLE) {
         for (int v = 0; v < 2 * nv; ++v) out[v] = NAN;
         free(st);
-        return status | OR_ST_INADMISSIBLE;
+        return status;
     }
 
     const double delta = oracle_delta(d, gamma);
@@ -207,7 +217,8 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
 /*
  * Bounds for a selection of elements.
  *   states  [d+2][n_elem*n_s] conserved variables, SoA, element-major nodes
- *   rowptr  [n_elem+1], cols[nnz]: element stencils (element ids)
+ *   rowptr  [n_elem+1], cols[nnz]: element stencils (element ids); bad rows
+ *           are flagged OR_ST_BAD_STENCIL with NaN bounds
  *   elems   [n_sel] element ids to evaluate (NULL: all, n_sel = n_elem)
  *   bounds  out [2(d+2)][n_sel]: rows (rho, m.., E)_min then (rho, m.., E)_max
  *   status  out [n_sel] or NULL
@@ -215,7 +226,7 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
  */
 int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
                   int grid_mode, const int* n, const double* lo, const double* hi, double k,
-                  int64_t n_elem, int n_s, const double* states,
+                  int64_t n_elem, int n_s, int64_t nnz, const double* states,
                   const int* rowptr, const int* cols,
                   const int64_t* elems, int64_t n_sel,
                   double* bounds, unsigned* status) {
@@ -223,13 +234,12 @@ int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
     for (int j = 0; j < d; ++j) if (n[j] < 2) return -1;
     if (oracle_delta(d, gamma) < 0.0) return -1;
     const int nv = d + 2;
-    const int64_t n_nodes = n_elem * n_s;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t q = 0; q < n_sel; ++q) {
         int64_t e = elems ? elems[q] : q;
         double out[2 * OR_MAXV];
         unsigned st = element_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k,
-                                     n_s, states, n_nodes, rowptr, cols, e, out);
+                                     n_s, states, n_elem, nnz, rowptr, cols, e, out);
         for (int v = 0; v < 2 * nv; ++v) bounds[(int64_t)v * n_sel + q] = out[v];
         if (status) status[q] = st;
     }

@@ -1,0 +1,16 @@
+"""Kinetic maximum-principle bounds and squeeze limiting on MI355X (gfx950).
+
+The compute lives in libkbl.so (hand-written HIP behind the C-ABI of
+include/kbl.h); this package only marshals torch tensors into those calls.
+Importing it does not load the library; the first call does, and fails
+loudly if it has not been built.
+"""
+
+from ._lib import (  # noqa: F401
+    GRID_GLOBAL, GRID_STENCIL, PREC_FP64, PREC_MIXED_BF16, PREC_MIXED_FP16,
+    ST_INADMISSIBLE, ST_RHO_FLOOR, ST_EPS_RULE, ST_LIMITED, ST_PSTEP, ST_PMEAN_FLOOR,
+    ST_MEAN_OUTSIDE, ST_BAD_BOUNDS, ST_BAD_STENCIL, KblError, LIB_PATH,
+)
+from .ops import compute_bounds, limit, make_params, make_vgrid  # noqa: F401
+
+__all__ = ["compute_bounds", "limit", "make_params", "make_vgrid", "KblError"]

@@ -1,0 +1,91 @@
+"""ctypes view of libkbl.so (include/kbl.h).  Argument marshalling only."""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkbl.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "kbl.h")
+
+KBL_OK = 0
+KBL_ERR_ARG = 1
+KBL_ERR_GAMMA = 2
+KBL_ERR_GRID = 3
+KBL_ERR_UNSUPPORTED = 4
+KBL_ERR_HIP = 5
+KBL_ERR_WORKSPACE = 6
+
+GRID_GLOBAL = 0
+GRID_STENCIL = 1
+
+PREC_FP64 = 0
+PREC_MIXED_BF16 = 1
+PREC_MIXED_FP16 = 2
+
+ST_INADMISSIBLE = 0x1
+ST_RHO_FLOOR = 0x2
+ST_EPS_RULE = 0x4
+ST_LIMITED = 0x8
+ST_PSTEP = 0x10
+ST_PMEAN_FLOOR = 0x20
+ST_MEAN_OUTSIDE = 0x40
+ST_BAD_BOUNDS = 0x80
+ST_BAD_STENCIL = 0x100
+
+
+class VGrid(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("n", C.c_int32 * 2), ("lo", C.c_double * 2),
+                ("hi", C.c_double * 2), ("k", C.c_double)]
+
+
+class Params(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("r_fac", C.c_double), ("rho_floor", C.c_double),
+                ("p_floor", C.c_double), ("eps_alpha", C.c_double), ("precision", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class KblError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _load().kbl_status_string(code).decode() if _lib is not None else str(code)
+        super().__init__(f"{where}: {msg} (status {code})")
+
+
+_lib = None
+
+
+def header_symbols():
+    """Entry points declared in include/kbl.h."""
+    txt = open(HEADER).read()
+    return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(kbl_\w+)\s*\(", txt, flags=re.M)))
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"libkbl.so is not built ({LIB_PATH}); run `python -m paper_2407_20966_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        lib.kbl_default_params.argtypes = [C.POINTER(Params), C.c_double]
+        lib.kbl_default_params.restype = None
+        lib.kbl_status_string.argtypes = [C.c_int]
+        lib.kbl_status_string.restype = C.c_char_p
+        lib.kbl_version.argtypes = []
+        lib.kbl_version.restype = C.c_int32
+        lib.kbl_compute_bounds.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
+                                           C.c_int64, P, P, P, C.POINTER(VGrid), P, P, P]
+        lib.kbl_compute_bounds.restype = C.c_int
+        lib.kbl_limit.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
+                                  P, P, P, P, P, P, P]
+        lib.kbl_limit.restype = C.c_int
+        _lib = lib
+    return _lib
+
+
+def lib():
+    return _load()

@@ -1,0 +1,104 @@
+"""Build libkbl.so (the HIP library behind include/kbl.h) for gfx950, in-tree.
+
+    python -m paper_2407_20966_amd.build
+
+Every call recompiles.  The library is written next to this file so that it
+travels with the source tree.
+"""
+
+from __future__ import annotations
+
+import glob
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libkbl.so")
+ARCH = os.environ.get("KBL_OFFLOAD_ARCH", "gfx950")
+
+HIP_FLAGS = [
+    f"--offload-arch={ARCH}",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    # no packed FP32 instructions anywhere in device code
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+    "-Wno-unused-function",
+]
+
+
+def hipcc() -> str:
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found: the HIP toolchain is required to build libkbl")
+
+
+# Per-source device flags.  The bounds kernels validate every input before
+# their hot loop, which is then NaN-free: without NaN semantics the running
+# min/max need no canonicalisation (one VALU op per min/max, not two).
+SOURCE_FLAGS = {
+    "bounds_fp64.hip": ["-fno-honor-nans"],
+}
+
+
+def sources():
+    return sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+
+
+def _run(cmd, verbose):
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    # the host pass does not know the packed-fp32 target feature; that warning is expected
+    noise = [ln for ln in res.stderr.splitlines()
+             if ln.strip() and "packed-fp32-ops" not in ln and "not a recognized feature" not in ln
+             and "--hip-link" not in ln]
+    if res.returncode != 0:
+        sys.stderr.write(res.stderr)
+        raise RuntimeError("hipcc failed: " + " ".join(cmd))
+    if noise and verbose:
+        sys.stderr.write("\n".join(noise) + "\n")
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    objdir = os.path.join(ROOT, "_build", "kbl")
+    os.makedirs(objdir, exist_ok=True)
+    objs = []
+    compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
+    for src in sources():
+        obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
+        cmd = ([hipcc()] + compile_flags + SOURCE_FLAGS.get(os.path.basename(src), [])
+               + list(extra) + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src])
+        _run(cmd, verbose)
+        objs.append(obj)
+    out_tmp = LIB + ".tmp"
+    _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs, verbose)
+    os.replace(out_tmp, LIB)
+    return LIB
+
+
+def asm(out_dir: str, extra=()) -> list:
+    """Emit device assembly of every source (inspection only)."""
+    os.makedirs(out_dir, exist_ok=True)
+    outs = []
+    for src in sources():
+        base = os.path.splitext(os.path.basename(src))[0]
+        out = os.path.join(out_dir, base + ".s")
+        cmd = [hipcc(), f"--offload-arch={ARCH}", "-O3", "-std=c++17",
+               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+               "--cuda-device-only", "-S", "-I", os.path.join(ROOT, "include"),
+               "-o", out, src] + SOURCE_FLAGS.get(os.path.basename(src), []) + list(extra)
+        subprocess.check_call(cmd)
+        outs.append(out)
+    return outs
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,57 @@
+// Internal declarations shared by the HIP translation units of libkbl.
+// Not part of the public interface (include/kbl.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/kbl.h"
+
+namespace kbl {
+
+constexpr double kPi = 3.141592653589793238462643383279502884;
+
+// Arguments of the bounds kernels, passed by value.
+struct BoundsArgs {
+    const double* states;
+    const int32_t* rowptr;
+    const int32_t* cols;
+    double* bounds;
+    uint32_t* status;
+    int64_t n_elem;
+    int64_t n_nodes;
+    int64_t nnz;
+    int32_t n_s;
+    int32_t grid_mode;
+    int32_t nx, ny;
+    double lo0, lo1, hi0, hi1, k;
+    double gm1;         // gamma - 1
+    double half_delta;  // delta / 2, delta = 2/(gamma-1) - d
+    double r_fac;
+    double rho_floor;
+};
+
+// Arguments of the limiter kernel.
+constexpr int kMaxLimitNodes = 64;
+struct LimitArgs {
+    const double* solution;
+    const double* bounds;
+    double* limited;
+    double* alpha;
+    uint32_t* status;
+    int64_t n_elem;
+    int64_t n_nodes;
+    int32_t n_s;
+    double gm1;
+    double p_floor;
+    double eps;
+    double inv_csum;                 // 1 / sum_j c_j
+    double c[kMaxLimitNodes];        // element quadrature weights
+};
+
+// Host-side launchers (one per translation unit).  They return hipSuccess or
+// the launch error; argument checking happened before.
+hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream);
+hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
+
+}  // namespace kbl

@@ -1,0 +1,165 @@
+// FP64 coupled squeeze limiter and pressure step (steps 5-7 of the overview
+// in Sec. 3.9), gfx950.
+//
+// HBM-bound: each node is read once and written once.  One lane owns one node
+// (all d+2 variables); the G = next power of two >= n_s lanes of an element
+// form an aligned lane group inside a wave64, so the element reductions (the
+// weighted mean, the nodal max/min per variable and the minimum pressure) are
+// xor-shuffles within the group.  Consecutive lanes read consecutive nodes of
+// the SoA rows, so loads and stores are coalesced.
+//  - mean with positive weights c_j (Assumption (iii)(a) of Sec. 4);
+//  - alpha_i per component (eq. alpha) with the epsilon rule, coupled by the
+//    minimum (eq. limiter);
+//  - P_min over the limited nodes (eq. pmin) and, below the floor, the second
+//    blend with alpha_P (eq. doublelimit).  An undefined pressure counts as
+//    below the floor.  P(mean) <= floor gives alpha_P = 0 (flattened element).
+#include <math.h>
+
+#include "kbl_internal.h"
+
+namespace kbl {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr double kInf = __builtin_inf();
+
+template <int G>
+__device__ __forceinline__ double grp_sum(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+template <int G>
+__device__ __forceinline__ double grp_min(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+template <int G>
+__device__ __forceinline__ double grp_max(double v) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+template <int D>
+__device__ __forceinline__ double pressure(double gm1, const double* w) {
+    const double mm = (D == 2) ? w[1] * w[1] + w[2] * w[2] : w[1] * w[1];
+    return gm1 * (w[D + 1] - 0.5 * mm / w[0]);
+}
+
+template <int D, int G>
+__global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
+    constexpr int NV = D + 2;
+    constexpr int EPB = kThreads / G;   // elements per workgroup
+    const int tid = threadIdx.x;
+    const int j = tid % G;
+    const int64_t e = (int64_t)blockIdx.x * EPB + tid / G;
+    // Lanes past the last element or past n_s take part in the shuffles with
+    // neutral values and never touch memory.
+    const bool live = (e < p.n_elem) && (j < p.n_s);
+    const int64_t node = live ? e * p.n_s + j : 0;
+
+    double w[NV];
+    const double c = live ? p.c[j] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = live ? p.solution[(int64_t)v * p.n_nodes + node] : 0.0;
+
+    double b[2 * NV];
+    bool bad_b = false;
+#pragma unroll
+    for (int v = 0; v < 2 * NV; ++v) {
+        b[v] = (e < p.n_elem) ? p.bounds[(int64_t)v * p.n_elem + e] : 0.0;
+        bad_b |= !isfinite(b[v]);
+    }
+
+    uint32_t st = 0;
+    double wbar[NV];
+    double amin = 1.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        wbar[v] = grp_sum<G>(c * w[v]) * p.inv_csum;
+        const double wmax = grp_max<G>(live ? w[v] : -kInf);
+        const double wmin = grp_min<G>(live ? w[v] : kInf);
+        if (wbar[v] < b[v] || wbar[v] > b[NV + v]) st |= KBL_ST_MEAN_OUTSIDE;
+        const double dp = wmax - wbar[v], dm = wmin - wbar[v];
+        double av;
+        if (fabs(dm) < p.eps || fabs(dp) < p.eps) {
+            av = 0.0;
+            st |= KBL_ST_EPS_RULE;
+        } else {
+            av = 1.0;
+            const double ru = fabs((b[NV + v] - wbar[v]) / dp);
+            const double rl = fabs((b[v] - wbar[v]) / dm);
+            if (ru < av) av = ru;
+            if (rl < av) av = rl;
+        }
+        if (av < amin) amin = av;
+    }
+    if (amin < 1.0) st |= KBL_ST_LIMITED;
+
+    double wt[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + amin * (w[v] - wbar[v]);
+
+    double P = live ? pressure<D>(p.gm1, wt) : kInf;
+    if (isnan(P)) P = -kInf;
+    const double pmin = grp_min<G>(P);
+    double aP = 1.0;
+    if (pmin < p.p_floor) {
+        st |= KBL_ST_PSTEP;
+        const double pbar = pressure<D>(p.gm1, wbar);
+        if (pbar > p.p_floor) aP = fabs((p.p_floor - pbar) / (pmin - pbar));
+        else { aP = 0.0; st |= KBL_ST_PMEAN_FLOOR; }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + aP * (wt[v] - wbar[v]);
+    }
+
+    if (bad_b) {
+        st = KBL_ST_BAD_BOUNDS;
+        amin = 1.0;
+        aP = 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) wt[v] = w[v];
+    }
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) p.limited[(int64_t)v * p.n_nodes + node] = wt[v];
+        if (j == 0) {
+            if (p.alpha) {
+                p.alpha[e] = amin;
+                p.alpha[p.n_elem + e] = aP;
+            }
+            if (p.status) p.status[e] = st;
+        }
+    }
+}
+
+template <int D, int G>
+hipError_t launch_g(const LimitArgs& a, hipStream_t stream) {
+    constexpr int EPB = kThreads / G;
+    const int64_t blocks = (a.n_elem + EPB - 1) / EPB;
+    if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((limit_fp64<D, G>), dim3((unsigned)blocks), dim3(kThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_d(const LimitArgs& a, hipStream_t stream) {
+    if (a.n_s <= 1) return launch_g<D, 1>(a, stream);
+    if (a.n_s <= 2) return launch_g<D, 2>(a, stream);
+    if (a.n_s <= 4) return launch_g<D, 4>(a, stream);
+    if (a.n_s <= 8) return launch_g<D, 8>(a, stream);
+    if (a.n_s <= 16) return launch_g<D, 16>(a, stream);
+    if (a.n_s <= 32) return launch_g<D, 32>(a, stream);
+    return launch_g<D, 64>(a, stream);
+}
+
+}  // namespace
+
+hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream) {
+    if (a.n_elem == 0) return hipSuccess;
+    return dim == 2 ? launch_d<2>(a, stream) : launch_d<1>(a, stream);
+}
+
+}  // namespace kbl

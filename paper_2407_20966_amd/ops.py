@@ -1,0 +1,129 @@
+"""PyTorch-facing calls of libkbl: tensors in, tensors out, nothing computed here.
+
+Every function checks tensor placement/dtype/layout, allocates outputs with
+torch, and forwards raw device pointers plus torch's current HIP stream to
+the C-ABI in include/kbl.h.  All arithmetic runs in the HIP kernels.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+from typing import Optional, Sequence, Tuple
+
+import torch
+
+from . import _lib as L
+
+
+def make_params(gamma: float, r_fac: float = 1e-3, rho_floor: float = 1e-12,
+                p_floor: float = 1e-12, eps_alpha: float = 1e-13,
+                precision: int = L.PREC_FP64) -> L.Params:
+    p = L.Params()
+    L.lib().kbl_default_params(C.byref(p), float(gamma))
+    p.r_fac = float(r_fac)
+    p.rho_floor = float(rho_floor)
+    p.p_floor = float(p_floor)
+    p.eps_alpha = float(eps_alpha)
+    p.precision = int(precision)
+    return p
+
+
+def make_vgrid(mode: int, n: Sequence[int], lo: Sequence[float] = (0.0, 0.0),
+               hi: Sequence[float] = (0.0, 0.0), k: float = 4.0) -> L.VGrid:
+    g = L.VGrid()
+    g.mode = int(mode)
+    nn = list(n) + [2] * (2 - len(n))
+    lo = list(lo) + [0.0] * (2 - len(lo))
+    hi = list(hi) + [0.0] * (2 - len(hi))
+    for j in range(2):
+        g.n[j] = int(nn[j])
+        g.lo[j] = float(lo[j])
+        g.hi[j] = float(hi[j])
+    g.k = float(k)
+    return g
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device: torch.device, stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream(device)
+    return C.c_void_p(s.cuda_stream)
+
+
+def _check(t: torch.Tensor, name: str, dtype: torch.dtype, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must live on a HIP device (got {t.device})")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def compute_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor, n_s: int,
+                   vgrid: L.VGrid, params: L.Params, out: Optional[torch.Tensor] = None,
+                   status: Optional[torch.Tensor] = None,
+                   stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Kinetic bounds [2(d+2), n_elem] (FP64) and per-element status (int32 view of uint32)."""
+    _check(states, "states", torch.float64)
+    dev = states.device
+    _check(rowptr, "rowptr", torch.int32, dev)
+    _check(cols, "cols", torch.int32, dev)
+    dim = states.shape[0] - 2
+    n_elem = rowptr.numel() - 1
+    if states.dim() != 2 or states.shape[1] != n_elem * n_s:
+        raise ValueError(f"states must be [d+2, n_elem*n_s] = [*, {n_elem * n_s}], got {tuple(states.shape)}")
+    if out is None:
+        out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
+    else:
+        _check(out, "out", torch.float64, dev)
+        if tuple(out.shape) != (2 * (dim + 2), n_elem):
+            raise ValueError("out has the wrong shape")
+    if status is None:
+        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    else:
+        _check(status, "status", torch.int32, dev)
+        if status.numel() != n_elem:
+            raise ValueError("status has the wrong size")
+    rc = L.lib().kbl_compute_bounds(C.byref(params), dim, n_elem, int(n_s), cols.numel(),
+                                    _ptr(states), _ptr(rowptr), _ptr(cols), C.byref(vgrid),
+                                    _ptr(out), _ptr(status), _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_compute_bounds")
+    return out, status
+
+
+def limit(solution: torch.Tensor, bounds: torch.Tensor, node_weights, n_s: int,
+          params: L.Params, out: Optional[torch.Tensor] = None,
+          alpha: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,
+          stream=None) -> Tuple[torch.Tensor, torch.Tensor, torch.Tensor]:
+    """Squeeze limiter + pressure step: (limited, alpha [2, n_elem], status)."""
+    _check(solution, "solution", torch.float64)
+    dev = solution.device
+    _check(bounds, "bounds", torch.float64, dev)
+    dim = solution.shape[0] - 2
+    n_elem = bounds.shape[1]
+    if solution.shape[1] != n_elem * n_s or bounds.shape[0] != 2 * (dim + 2):
+        raise ValueError("solution/bounds shapes do not match n_s and the dimension")
+    w = torch.as_tensor(node_weights, dtype=torch.float64).cpu().contiguous()
+    if w.numel() != n_s:
+        raise ValueError("node_weights must have n_s entries")
+    if out is None:
+        out = torch.empty_like(solution)
+    else:
+        _check(out, "out", torch.float64, dev)
+    if alpha is None:
+        alpha = torch.empty((2, n_elem), dtype=torch.float64, device=dev)
+    if status is None:
+        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    rc = L.lib().kbl_limit(C.byref(params), dim, n_elem, int(n_s), _ptr(solution), _ptr(bounds),
+                           C.c_void_p(w.data_ptr()), _ptr(out), _ptr(alpha), _ptr(status),
+                           _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_limit")
+    return out, alpha, status

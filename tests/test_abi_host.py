@@ -1,0 +1,159 @@
+"""Host-side checks of the C-ABI (no GPU needed, no kernel is launched).
+
+- libkbl.so loads and exports every entry point include/kbl.h declares;
+- the ctypes mirrors of kbl_params / kbl_vgrid match the C layout (gcc);
+- argument errors are returned synchronously, before any HIP call.
+"""
+
+import ctypes as C
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from paper_2407_20966_amd import _lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+FAKE = C.c_void_p(0x10000)   # never dereferenced: every call below fails validation first
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libkbl.so not built (run __graft_entry__.build())")
+    return L.lib()
+
+
+def test_header_declares_expected_entry_points():
+    syms = L.header_symbols()
+    for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
+              "kbl_default_params"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [s for s in L.header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True, text=True)
+    if out.returncode == 0:
+        exported = {ln.split()[-1] for ln in out.stdout.splitlines() if ln.strip()}
+        assert set(L.header_symbols()) <= exported
+
+
+def test_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "kbl.h"\n'
+        "int main(void){\n"
+        ' printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(kbl_params), offsetof(kbl_params, precision),'
+        " offsetof(kbl_params, eps_alpha), sizeof(kbl_vgrid), offsetof(kbl_vgrid, lo),"
+        " offsetof(kbl_vgrid, k));\n return 0;}\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals == [C.sizeof(L.Params), L.Params.precision.offset, L.Params.eps_alpha.offset,
+                    C.sizeof(L.VGrid), L.VGrid.lo.offset, L.VGrid.k.offset]
+
+
+def test_defaults_and_strings(lib):
+    p = L.Params()
+    lib.kbl_default_params(C.byref(p), 1.4)
+    assert (p.gamma, p.r_fac, p.rho_floor, p.p_floor, p.eps_alpha) == (1.4, 1e-3, 1e-12, 1e-12, 1e-13)
+    assert p.precision == L.PREC_FP64 and p.reserved == 0
+    for code in range(7):
+        assert lib.kbl_status_string(code)
+    assert lib.kbl_version() >= 100
+
+
+def _params(lib, gamma=1.4, **kw):
+    p = L.Params()
+    lib.kbl_default_params(C.byref(p), gamma)
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _grid(mode=L.GRID_STENCIL, n=(48, 48), lo=(-1, -1), hi=(1, 1), k=4.0):
+    g = L.VGrid()
+    g.mode = mode
+    g.n[0], g.n[1] = n
+    g.lo[0], g.lo[1] = lo
+    g.hi[0], g.hi[1] = hi
+    g.k = k
+    return g
+
+
+def _bounds(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20, ptrs=True):
+    P = FAKE if ptrs else None
+    return lib.kbl_compute_bounds(C.byref(p), dim, n_elem, n_s, nnz, P, P, P, C.byref(g), P, None, None)
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(dim=3), L.KBL_ERR_ARG),
+    (dict(dim=0), L.KBL_ERR_ARG),
+    (dict(n_elem=-1), L.KBL_ERR_ARG),
+    (dict(n_s=0), L.KBL_ERR_ARG),
+    (dict(nnz=-3), L.KBL_ERR_ARG),
+    (dict(ptrs=False), L.KBL_ERR_ARG),
+])
+def test_bounds_rejects_bad_sizes(lib, case, expect):
+    assert _bounds(lib, _params(lib), _grid(), **case) == expect
+
+
+@pytest.mark.parametrize("pkw,expect", [
+    (dict(gamma=1.0), L.KBL_ERR_GAMMA),
+    (dict(gamma=0.5), L.KBL_ERR_GAMMA),
+    (dict(gamma=2.5), L.KBL_ERR_GAMMA),          # delta = 2/1.5 - 2 < 0 in 2D
+    (dict(r_fac=1.0), L.KBL_ERR_ARG),
+    (dict(r_fac=-1e-3), L.KBL_ERR_ARG),
+    (dict(rho_floor=-1.0), L.KBL_ERR_ARG),
+    (dict(eps_alpha=float("nan")), L.KBL_ERR_ARG),
+    (dict(reserved=1), L.KBL_ERR_ARG),
+    (dict(precision=7), L.KBL_ERR_UNSUPPORTED),
+])
+def test_bounds_rejects_bad_params(lib, pkw, expect):
+    gamma = pkw.pop("gamma", 1.4)
+    assert _bounds(lib, _params(lib, gamma, **pkw), _grid()) == expect
+
+
+@pytest.mark.parametrize("gkw,expect", [
+    (dict(n=(1, 48)), L.KBL_ERR_GRID),
+    (dict(n=(48, 1)), L.KBL_ERR_GRID),
+    (dict(n=(65, 48)), L.KBL_ERR_GRID),
+    (dict(k=0.0), L.KBL_ERR_GRID),
+    (dict(k=float("inf")), L.KBL_ERR_GRID),
+    (dict(mode=L.GRID_GLOBAL, lo=(1, 0), hi=(1, 1)), L.KBL_ERR_GRID),
+    (dict(mode=L.GRID_GLOBAL, lo=(0, 0), hi=(1, float("nan"))), L.KBL_ERR_GRID),
+    (dict(mode=5), L.KBL_ERR_GRID),
+])
+def test_bounds_rejects_bad_grid(lib, gkw, expect):
+    assert _bounds(lib, _params(lib), _grid(**gkw)) == expect
+
+
+def test_bounds_1d_grid_limit(lib):
+    g = _grid(n=(4097, 2))
+    assert _bounds(lib, _params(lib), g, dim=1) == L.KBL_ERR_GRID
+
+
+def _limit(lib, p, w, dim=2, n_elem=4, n_s=None):
+    n_s = len(w) if n_s is None else n_s
+    wa = np.ascontiguousarray(w, dtype=np.float64)
+    return lib.kbl_limit(C.byref(p), dim, n_elem, n_s, FAKE, FAKE,
+                         wa.ctypes.data_as(C.c_void_p), FAKE, None, None, None)
+
+
+def test_limit_rejects_bad_weights(lib):
+    p = _params(lib)
+    assert _limit(lib, p, [1.0, 0.0, 1.0]) == L.KBL_ERR_ARG
+    assert _limit(lib, p, [1.0, -1.0, 1.0]) == L.KBL_ERR_ARG
+    assert _limit(lib, p, [1.0, float("nan")]) == L.KBL_ERR_ARG
+    assert _limit(lib, p, [1.0] * 65) == L.KBL_ERR_ARG      # n_s > 64
+    assert lib.kbl_limit(C.byref(p), 2, 4, 4, FAKE, FAKE, None, FAKE, None, None, None) == L.KBL_ERR_ARG
+
+
+def test_limit_rejects_bad_params(lib):
+    assert _limit(lib, _params(lib, 1.0), [1.0, 1.0]) == L.KBL_ERR_GAMMA
+    assert _limit(lib, _params(lib), [1.0, 1.0], dim=4) == L.KBL_ERR_ARG
+    assert _limit(lib, _params(lib), [1.0, 1.0], n_elem=-2) == L.KBL_ERR_ARG
