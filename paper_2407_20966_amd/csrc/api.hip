@@ -1,6 +1,7 @@
 // C-ABI entry points of libkbl: host-side argument checks, then launches on
 // the caller's stream.  See include/kbl.h for the contract.
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include "kbl_internal.h"
@@ -107,7 +108,13 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
     a.half_delta = half_delta;
     a.r_fac = params->r_fac;
     a.rho_floor = params->rho_floor;
-    hipError_t err = kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream);
+    // KBL_BOUNDS_TILE (tuning knob) forces a 2D tile configuration index
+    int tile = -1;
+    if (const char* env = getenv("KBL_BOUNDS_TILE")) {
+        tile = atoi(env);
+        if (dim == 2 && !kbl::bounds_tile_fits_2d(tile, g.n[0], g.n[1])) tile = -1;
+    }
+    hipError_t err = kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream, tile);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 

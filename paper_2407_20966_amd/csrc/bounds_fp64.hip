@@ -1,18 +1,20 @@
 // FP64 kinetic bounds (steps 1-3 of the overview in Sec. 3.9), gfx950.
 //
-// One workgroup of 256 threads (four wave64) owns one element at a time.
-//  1. The stencil states (every node of every element of the CSR row) are
-//     read once to check admissibility (Assumption (i) of Sec. 4) and, in
-//     STENCIL mode, to reduce the velocity box of eq. truncdomain.
-//  2. The states are then streamed through LDS in chunks.  For each state i
-//     the log-Maxwellian  q_i(u) = ln rho_i - (d/2) ln(2 pi theta_i)
-//     - |u - U_i|^2 / (2 theta_i)  is separable on the Cartesian velocity
-//     grid: q_i = A_i[jx] + B_i[jy].  The chunk's A, A + ln(theta delta/2)
-//     and B tables are built once in LDS, so the hot loop costs two adds and
-//     four min/max per (state, velocity node) pair.  Because exp is monotone,
-//     min_i g_i = exp(min_i q_i) (eq. fminmax), and likewise for the internal
-//     part g_I = (theta delta / 2) g (Sec. 3.6): four running extrema per node
-//     stay in registers and only four exp per node are taken at the end.
+// One workgroup (1-4 wave64) owns one element at a time.
+//  1. Prologue: every stencil state (every node of every element of the CSR
+//     row) is read once, checked for admissibility (Assumption (i) of Sec. 4)
+//     and turned into the coefficients of its log-Maxwellian
+//       q_i(u) = ln rho_i - (d/2) ln(2 pi theta_i) - |u - U_i|^2 / (2 theta_i),
+//     which are staged in LDS; in STENCIL mode the velocity box of
+//     eq. truncdomain is reduced on the way.
+//  2. Hot loop over the states: q_i is separable on the Cartesian velocity
+//     grid, q_i = A_i[jx] + B_i[jy].  Each thread evaluates A (and
+//     A + ln(theta delta / 2)) for its x nodes and B for its y nodes, then
+//     spends two adds and four min/max per (state, node) pair.  Because exp is
+//     monotone, min_i g_i = exp(min_i q_i) (eq. fminmax), and likewise for the
+//     internal part g_I = (theta delta / 2) g (Sec. 3.6): four running extrema
+//     per node stay in registers and only four exp per node are taken at the
+//     end.  (A tile variant reads B from an LDS table instead.)
 //  3. Relaxation (eq. relaxed), trapezoid weights (Sec. 3.7) and the moment
 //     contraction (eq. rhobounds, Ebounds, mmbounds, mpbounds) are done per
 //     node, then reduced across the workgroup in a fixed order (bitwise
@@ -30,7 +32,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kWaves = kThreads / 64;
-constexpr int kChunk = 16;          // stencil states per LDS chunk
+constexpr int kMaxStates = 256;     // stencil states staged in LDS at once
 constexpr double kInf = __builtin_inf();
 
 struct Prim {
@@ -79,26 +81,53 @@ __device__ __forceinline__ double wave_max(double v) {
     return v;
 }
 
-// Shared scratch for the per-element prologue and epilogue.
+// Shared scratch for the per-element prologue and epilogue (up to 4 waves).
 struct Red {
     double v[kWaves][8];
     uint32_t flags;
 };
 
-// Prologue: admissibility + velocity box.  Returns status bits (uniform).
+// Per-state coefficients of the log-Maxwellian (Sec. 2.2, Sec. 3.6).
+struct Coef {
+    double a;    // ln rho - (d/2) ln(2 pi theta)
+    double al;   // a + ln(theta delta / 2)   (-inf when delta == 0)
+    double ux, uy;
+    double nk;   // -1 / (2 theta)
+};
+
 template <int D>
-__device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t e, int64_t row0, int64_t S,
-                                     Red& red, double box[4]) {
+__device__ __forceinline__ Coef make_coef(const BoundsArgs& p, const Prim& s) {
+    Coef c;
+    c.a = log(s.rho) - (0.5 * D) * log(2.0 * kPi * s.th);
+    c.al = (p.half_delta > 0.0) ? c.a + log(s.th * p.half_delta) : -kInf;
+    c.ux = s.ux;
+    c.uy = s.uy;
+    c.nk = -0.5 / s.th;
+    return c;
+}
+
+// Stencil state s of the row starting at row0 (the caller validated the row).
+__device__ __forceinline__ int64_t state_node(const BoundsArgs& p, int64_t row0, int64_t s) {
+    const int32_t col = p.cols[row0 + s / p.n_s];
+    return (int64_t)col * p.n_s + s % p.n_s;
+}
+
+// Prologue: admissibility, velocity box, and the coefficients of the first
+// kMaxStates states staged in sC.  Returns status bits (uniform).
+template <int D, int NT>
+__device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t S, Red& red,
+                                     Coef* sC, double box[4]) {
+    constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     uint32_t bad = 0;
     double lx = kInf, hx = -kInf, ly = kInf, hy = -kInf;
-    for (int64_t s = tid; s < S; s += kThreads) {
-        const int64_t r = row0 + s / p.n_s;
-        const int32_t col = p.cols[r];
+    for (int64_t s = tid; s < S; s += NT) {
+        const int32_t col = p.cols[row0 + s / p.n_s];
         if (col < 0 || col >= p.n_elem) { bad |= KBL_ST_BAD_STENCIL; continue; }
         const Prim st = load_prim<D>(p, (int64_t)col * p.n_s + s % p.n_s);
         if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
+        if (s < kMaxStates) sC[s] = make_coef<D>(p, st);
         if (p.grid_mode == KBL_GRID_STENCIL) {
             const double sd = sqrt(st.th);
             lx = fmin(lx, st.ux - p.k * sd);
@@ -120,7 +149,7 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t e, int64_t row
     if (p.grid_mode == KBL_GRID_STENCIL) {
         box[0] = red.v[0][0]; box[1] = red.v[0][1]; box[2] = red.v[0][2]; box[3] = red.v[0][3];
 #pragma unroll
-        for (int w = 1; w < kWaves; ++w) {
+        for (int w = 1; w < NW; ++w) {
             box[0] = fmin(box[0], red.v[w][0]); box[1] = fmax(box[1], red.v[w][1]);
             box[2] = fmin(box[2], red.v[w][2]); box[3] = fmax(box[3], red.v[w][3]);
         }
@@ -132,23 +161,15 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t e, int64_t row
     return flags;
 }
 
-// Per-state coefficients of the log-Maxwellian (Sec. 2.2, Sec. 3.6).
-struct Coef {
-    double a;    // ln rho - (d/2) ln(2 pi theta)
-    double l;    // ln(theta delta / 2)  (-inf when delta == 0)
-    double ux, uy;
-    double kap;  // 1 / (2 theta)
-};
-
-template <int D>
-__device__ __forceinline__ Coef make_coef(const BoundsArgs& p, const Prim& s) {
-    Coef c;
-    c.a = log(s.rho) - (0.5 * D) * log(2.0 * kPi * s.th);
-    c.l = (p.half_delta > 0.0) ? log(s.th * p.half_delta) : -kInf;
-    c.ux = s.ux;
-    c.uy = s.uy;
-    c.kap = 0.5 / s.th;
-    return c;
+// Stage the coefficients of states [c0, c0 + cn) into sC (chunks after the
+// first, for stencils larger than kMaxStates).  Bracketed by barriers.
+template <int D, int NT>
+__device__ __forceinline__ void stage_chunk(const BoundsArgs& p, int64_t row0, int64_t c0, int cn,
+                                            Coef* sC) {
+    __syncthreads();
+    for (int s = threadIdx.x; s < cn; s += NT)
+        sC[s] = make_coef<D>(p, load_prim<D>(p, state_node(p, row0, c0 + s)));
+    __syncthreads();
 }
 
 template <int D>
@@ -178,40 +199,47 @@ __device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32
 }
 
 // Fixed-order workgroup sum of NV partials; result valid in thread 0.
-template <int NV>
+template <int NT, int NV>
 __device__ __forceinline__ void block_sum(double* part, Red& red) {
+    constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 0; i < NV; ++i) part[i] = wave_sum(part[i]);
-    if (lane == 0) {
+    if (NW > 1) {
+        if (lane == 0) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) red.v[wid][i] = part[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double s = red.v[0][i];
-#pragma unroll
-            for (int w = 1; w < kWaves; ++w) s += red.v[w][i];
-            part[i] = s;
+            for (int i = 0; i < NV; ++i) red.v[wid][i] = part[i];
         }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                double s = red.v[0][i];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) s += red.v[w][i];
+                part[i] = s;
+            }
+        }
+        __syncthreads();
     }
-    __syncthreads();
 }
 
 // ---------------------------------------------------------------- 2D kernel
-template <int TX, int TY>
-__global__ __launch_bounds__(kThreads) void bounds_fp64_2d(BoundsArgs p) {
-    constexpr int NXM = 16 * TX, NYM = 16 * TY;
-    __shared__ double sA[kChunk][NXM];
-    __shared__ double sAI[kChunk][NXM];
-    __shared__ double sB[kChunk][NYM];
-    __shared__ Coef sC[kChunk];
+// BX x BY threads; thread (tx, ty) owns velocity nodes (tx + BX i, ty + BY j),
+// i < TX, j < TY.  BTAB = 1 reads B from an LDS table built per sub-chunk of
+// kTabStates states (fewer VALU ops, more LDS traffic and barriers).
+template <int BX, int BY, int TX, int TY, int BTAB>
+__global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
+    constexpr int NT = BX * BY;
+    constexpr int NYM = BY * TY;
+    constexpr int kTabStates = 32;
+    static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    __shared__ Coef sC[kMaxStates];
+    __shared__ double sB[BTAB ? kTabStates : 1][BTAB ? NYM : 1];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4;
+    const int tx = tid % BX, ty = tid / BX;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
 
     for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
@@ -222,7 +250,7 @@ __global__ __launch_bounds__(kThreads) void bounds_fp64_2d(BoundsArgs p) {
         }
         const int64_t S = (row1 - row0) * p.n_s;
         double box[4];
-        const uint32_t flags = stencil_prologue<2>(p, e, row0, S, red, box);
+        const uint32_t flags = stencil_prologue<2, NT>(p, row0, S, red, sC, box);
         if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
             if (tid == 0) store_nan<2>(p, e, flags);
             continue;
@@ -230,6 +258,19 @@ __global__ __launch_bounds__(kThreads) void bounds_fp64_2d(BoundsArgs p) {
         const double lox = box[0], loy = box[2];
         const double hx = (box[1] - box[0]) / (double)(p.nx - 1);
         const double hy = (box[3] - box[2]) / (double)(p.ny - 1);
+
+        // node coordinates (clamped into the grid for the ragged tail)
+        double ux[TX], uy[TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+            const int j = tx + BX * i;
+            ux[i] = lox + (j < p.nx ? j : p.nx - 1) * hx;
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int jj = ty + BY * j;
+            uy[j] = loy + (jj < p.ny ? jj : p.ny - 1) * hy;
+        }
 
         double qtn[TX][TY], qtx[TX][TY], qin[TX][TY], qix[TX][TY];
 #pragma unroll
@@ -239,47 +280,54 @@ __global__ __launch_bounds__(kThreads) void bounds_fp64_2d(BoundsArgs p) {
                 qtn[i][j] = kInf; qtx[i][j] = -kInf; qin[i][j] = kInf; qix[i][j] = -kInf;
             }
 
-        for (int64_t c0 = 0; c0 < S; c0 += kChunk) {
-            const int cn = (int)((S - c0) < kChunk ? (S - c0) : kChunk);
-            __syncthreads();
-            if (tid < cn) {
-                const int64_t s = c0 + tid;
-                const int32_t col = p.cols[row0 + s / p.n_s];
-                sC[tid] = make_coef<2>(p, load_prim<2>(p, (int64_t)col * p.n_s + s % p.n_s));
-            }
-            __syncthreads();
-            for (int idx = tid; idx < cn * NXM; idx += kThreads) {
-                const int s = idx / NXM, j = idx - s * NXM;
-                const int jc = j < p.nx ? j : p.nx - 1;
-                const double d = (lox + jc * hx) - sC[s].ux;
-                const double A = fma(-sC[s].kap * d, d, sC[s].a);
-                sA[s][j] = A;
-                sAI[s][j] = A + sC[s].l;
-            }
-            for (int idx = tid; idx < cn * NYM; idx += kThreads) {
-                const int s = idx / NYM, j = idx - s * NYM;
-                const int jc = j < p.ny ? j : p.ny - 1;
-                const double d = (loy + jc * hy) - sC[s].uy;
-                sB[s][j] = -sC[s].kap * d * d;
-            }
-            __syncthreads();
-            for (int s = 0; s < cn; ++s) {
-                double a[TX], ai[TX], b[TY];
-#pragma unroll
-                for (int i = 0; i < TX; ++i) { a[i] = sA[s][tx + 16 * i]; ai[i] = sAI[s][tx + 16 * i]; }
-#pragma unroll
-                for (int j = 0; j < TY; ++j) b[j] = sB[s][ty + 16 * j];
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
-#pragma unroll
-                    for (int j = 0; j < TY; ++j) {
-                        const double q = a[i] + b[j];
-                        const double qi = ai[i] + b[j];
-                        qtn[i][j] = fmin(qtn[i][j], q);
-                        qtx[i][j] = fmax(qtx[i][j], q);
-                        qin[i][j] = fmin(qin[i][j], qi);
-                        qix[i][j] = fmax(qix[i][j], qi);
+        for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
+            const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
+            if (c0 > 0) stage_chunk<2, NT>(p, row0, c0, cn, sC);
+            for (int t0 = 0; t0 < cn; t0 += (BTAB ? kTabStates : kMaxStates)) {
+                const int tn = BTAB ? ((cn - t0) < kTabStates ? (cn - t0) : kTabStates) : cn;
+                if (BTAB) {
+                    __syncthreads();
+                    for (int idx = tid; idx < tn * NYM; idx += NT) {
+                        const int s = idx / NYM, j = idx - s * NYM;
+                        const int jc = j < p.ny ? j : p.ny - 1;
+                        const double d = (loy + jc * hy) - sC[t0 + s].uy;
+                        sB[s][j] = (sC[t0 + s].nk * d) * d;
                     }
+                    __syncthreads();
+                }
+#pragma unroll 2
+                for (int s = 0; s < tn; ++s) {
+                    const Coef c = sC[t0 + s];
+                    double a[TX], ai[TX], b[TY];
+#pragma unroll
+                    for (int i = 0; i < TX; ++i) {
+                        const double d = ux[i] - c.ux;
+                        const double t = c.nk * d;
+                        a[i] = fma(t, d, c.a);
+                        ai[i] = fma(t, d, c.al);
+                    }
+                    if (BTAB) {
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) b[j] = sB[s][ty + BY * j];
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            const double d = uy[j] - c.uy;
+                            b[j] = (c.nk * d) * d;
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < TX; ++i)
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            const double q = a[i] + b[j];
+                            const double qi = ai[i] + b[j];
+                            qtn[i][j] = fmin(qtn[i][j], q);
+                            qtx[i][j] = fmax(qtx[i][j], q);
+                            qin[i][j] = fmin(qin[i][j], qi);
+                            qix[i][j] = fmax(qix[i][j], qi);
+                        }
+                }
             }
         }
 
@@ -287,42 +335,43 @@ __global__ __launch_bounds__(kThreads) void bounds_fp64_2d(BoundsArgs p) {
         double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
-            const int jx = tx + 16 * i;
+            const int jx = tx + BX * i;
             if (jx >= p.nx) continue;
-            const double ux = lox + jx * hx;
             const double wx = hx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
-                const int jy = ty + 16 * j;
+                const int jy = ty + BY * j;
                 if (jy >= p.ny) continue;
-                const double uy = loy + jy * hy;
                 const double M = wx * (hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
                 const double ftn = rm * exp(qtn[i][j]);
                 const double ftx = rp * exp(qtx[i][j]);
                 const double fin = rm * exp(qin[i][j]);
                 const double fix = rp * exp(qix[i][j]);
-                const double hu2 = 0.5 * ux * ux + 0.5 * uy * uy;
+                const double hu2 = 0.5 * ux[i] * ux[i] + 0.5 * uy[j] * uy[j];
                 part[0] += M * ftn;
                 part[1] += M * ftx;
                 part[2] += M * (hu2 * ftn + fin);
                 part[3] += M * (hu2 * ftx + fix);
-                if (ux < 0.0) { part[4] += M * ux * ftx; part[5] += M * ux * ftn; }
-                else          { part[4] += M * ux * ftn; part[5] += M * ux * ftx; }
-                if (uy < 0.0) { part[6] += M * uy * ftx; part[7] += M * uy * ftn; }
-                else          { part[6] += M * uy * ftn; part[7] += M * uy * ftx; }
+                if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
+                else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
+                if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
+                else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
+                // one node at a time: keeps the exp temporaries of different
+                // nodes from being interleaved (register pressure)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
-        block_sum<8>(part, red);
+        block_sum<NT, 8>(part, red);
         if (tid == 0) store_bounds<2>(p, e, part, flags);
     }
 }
 
 // ---------------------------------------------------------------- 1D kernel
-// No separability to exploit: each pair costs sub, mul, fma (+ add for the
-// internal part) before the four min/max.  Coefficients are broadcast from LDS.
+// No separability to exploit: each pair costs sub, mul and two fma before the
+// four min/max.  Coefficients are broadcast from LDS.
 template <int NT, int T>
 __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
-    __shared__ Coef sC[kChunk];
+    __shared__ Coef sC[kMaxStates];
     __shared__ Red red;
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
@@ -334,35 +383,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
         }
         const int64_t S = (row1 - row0) * p.n_s;
         double box[4];
-        uint32_t flags;
-        if constexpr (NT == kThreads) {
-            flags = stencil_prologue<1>(p, e, row0, S, red, box);
-        } else {
-            // small workgroups: one wave does the prologue serially-strided
-            __shared__ double sbox[2];
-            __shared__ uint32_t sflags;
-            if (tid < 64) {
-                uint32_t bad = 0;
-                double lx = kInf, hx = -kInf;
-                for (int64_t s = tid; s < S; s += 64) {
-                    const int32_t col = p.cols[row0 + s / p.n_s];
-                    if (col < 0 || col >= p.n_elem) { bad |= KBL_ST_BAD_STENCIL; continue; }
-                    const Prim st = load_prim<1>(p, (int64_t)col * p.n_s + s % p.n_s);
-                    if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
-                    const double sd = sqrt(st.th);
-                    lx = fmin(lx, st.ux - p.k * sd);
-                    hx = fmax(hx, st.ux + p.k * sd);
-                }
-                lx = wave_min(lx); hx = wave_max(hx);
-                for (int o = 32; o > 0; o >>= 1) bad |= (uint32_t)__shfl_xor((int)bad, o, 64);
-                if (tid == 0) { sbox[0] = lx; sbox[1] = hx; sflags = bad; }
-            }
-            __syncthreads();
-            if (p.grid_mode == KBL_GRID_STENCIL) { box[0] = sbox[0]; box[1] = sbox[1]; }
-            else { box[0] = p.lo0; box[1] = p.hi0; }
-            flags = sflags;
-            __syncthreads();
-        }
+        const uint32_t flags = stencil_prologue<1, NT>(p, row0, S, red, sC, box);
         if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
             if (tid == 0) store_nan<1>(p, e, flags);
             continue;
@@ -376,24 +397,17 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
             u[i] = lo + (j < p.nx ? j : p.nx - 1) * h;
             qtn[i] = kInf; qtx[i] = -kInf; qin[i] = kInf; qix[i] = -kInf;
         }
-        for (int64_t c0 = 0; c0 < S; c0 += kChunk) {
-            const int cn = (int)((S - c0) < kChunk ? (S - c0) : kChunk);
-            __syncthreads();
-            if (tid < cn) {
-                const int64_t s = c0 + tid;
-                const int32_t col = p.cols[row0 + s / p.n_s];
-                sC[tid] = make_coef<1>(p, load_prim<1>(p, (int64_t)col * p.n_s + s % p.n_s));
-            }
-            __syncthreads();
+        for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
+            const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
+            if (c0 > 0) stage_chunk<1, NT>(p, row0, c0, cn, sC);
             for (int s = 0; s < cn; ++s) {
                 const Coef c = sC[s];
-                const double aI = c.a + c.l;
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     const double d = u[i] - c.ux;
-                    const double t = -c.kap * d;
+                    const double t = c.nk * d;
                     const double q = fma(t, d, c.a);
-                    const double qi = fma(t, d, aI);
+                    const double qi = fma(t, d, c.al);
                     qtn[i] = fmin(qtn[i], q);
                     qtx[i] = fmax(qtx[i], q);
                     qin[i] = fmin(qin[i], qi);
@@ -418,24 +432,9 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
             part[3] += M * (hu2 * ftx + fix);
             if (u[i] < 0.0) { part[4] += M * u[i] * ftx; part[5] += M * u[i] * ftn; }
             else            { part[4] += M * u[i] * ftn; part[5] += M * u[i] * ftx; }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if constexpr (NT == kThreads) {
-            block_sum<6>(part, red);
-        } else {
-            const int lane = tid & 63, wid = tid >> 6;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) part[i] = wave_sum(part[i]);
-            if (lane == 0)
-                for (int i = 0; i < 6; ++i) red.v[wid][i] = part[i];
-            __syncthreads();
-            if (tid == 0)
-                for (int i = 0; i < 6; ++i) {
-                    double s = red.v[0][i];
-                    for (int w = 1; w < NT / 64; ++w) s += red.v[w][i];
-                    part[i] = s;
-                }
-            __syncthreads();
-        }
+        block_sum<NT, 6>(part, red);
         if (tid == 0) store_bounds<1>(p, e, part, flags);
     }
 }
@@ -447,17 +446,57 @@ hipError_t launch(K kernel, int threads, const BoundsArgs& a, hipStream_t stream
     return hipGetLastError();
 }
 
+// 2D tile configurations: (BX, BY, TX, TY, BTAB) covers nx <= BX*TX, ny <= BY*TY.
+struct Tile2D {
+    int bx, by, tx, ty, btab;
+    hipError_t (*fn)(const BoundsArgs&, hipStream_t);
+};
+
+template <int BX, int BY, int TX, int TY, int BTAB>
+hipError_t launch_2d(const BoundsArgs& a, hipStream_t stream) {
+    return launch(bounds_fp64_2d<BX, BY, TX, TY, BTAB>, BX * BY, a, stream);
+}
+
+#define KBL_TILE(BX, BY, TX, TY, M) {BX, BY, TX, TY, M, launch_2d<BX, BY, TX, TY, M>}
+constexpr Tile2D kTiles2D[] = {
+    KBL_TILE(16, 16, 1, 1, 0),   // 0: n <= 16
+    KBL_TILE(16, 16, 2, 2, 0),   // 1: n <= 32
+    KBL_TILE(16, 16, 3, 3, 0),   // 2: n <= 48
+    KBL_TILE(16, 16, 3, 3, 1),   // 3: n <= 48, B from LDS
+    KBL_TILE(16, 8, 3, 6, 0),    // 4: n <= 48, two waves
+    KBL_TILE(16, 16, 4, 4, 0),   // 5: n <= 64
+    KBL_TILE(16, 16, 4, 4, 1),   // 6: n <= 64, B from LDS
+    KBL_TILE(32, 8, 2, 8, 1),    // 7: n <= 64, B from LDS
+    KBL_TILE(16, 16, 2, 4, 0),   // 8: nx <= 32, ny <= 64
+    KBL_TILE(16, 16, 4, 2, 0),   // 9: nx <= 64, ny <= 32
+};
+#undef KBL_TILE
+constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
+
+int default_tile_2d(int nx, int ny) {
+    const int n = nx > ny ? nx : ny;
+    if (n <= 16) return 0;
+    if (n <= 32) return 1;
+    if (n <= 48) return 3;
+    return 5;
+}
+
 }  // namespace
 
-hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream) {
+int bounds_tile_count_2d() { return kNumTiles2D; }
+
+bool bounds_tile_fits_2d(int tile, int nx, int ny) {
+    if (tile < 0 || tile >= kNumTiles2D) return false;
+    const Tile2D& t = kTiles2D[tile];
+    return nx <= t.bx * t.tx && ny <= t.by * t.ty;
+}
+
+hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile) {
     if (a.n_elem == 0) return hipSuccess;
     if (dim == 2) {
-        const int nmax = a.nx > a.ny ? a.nx : a.ny;
-        if (nmax <= 16) return launch(bounds_fp64_2d<1, 1>, kThreads, a, stream);
-        if (nmax <= 32) return launch(bounds_fp64_2d<2, 2>, kThreads, a, stream);
-        if (nmax <= 48) return launch(bounds_fp64_2d<3, 3>, kThreads, a, stream);
-        if (nmax <= 64) return launch(bounds_fp64_2d<4, 4>, kThreads, a, stream);
-        return hipErrorInvalidValue;
+        if (tile < 0) tile = default_tile_2d(a.nx, a.ny);
+        if (!bounds_tile_fits_2d(tile, a.nx, a.ny)) return hipErrorInvalidValue;
+        return kTiles2D[tile].fn(a, stream);
     }
     if (a.nx <= 64) return launch(bounds_fp64_1d<64, 1>, 64, a, stream);
     if (a.nx <= 256) return launch(bounds_fp64_1d<256, 1>, kThreads, a, stream);

@@ -51,7 +51,10 @@ struct LimitArgs {
 
 // Host-side launchers (one per translation unit).  They return hipSuccess or
 // the launch error; argument checking happened before.
-hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream);
+// tile < 0 selects the default 2D tile for the grid size.
+hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile);
+int bounds_tile_count_2d();
+bool bounds_tile_fits_2d(int tile, int nx, int ny);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
 
 }  // namespace kbl

@@ -19,7 +19,8 @@ def stencil_momentum_scale(wl, elems=None):
     el = node_scale.reshape(wl.n_elem, wl.n_s).max(1)
     starts = wl.rowptr[:-1].astype(np.int64)
     sizes = np.diff(wl.rowptr.astype(np.int64))
-    full = np.maximum.reduceat(el[wl.cols], starts)
+    cols = np.clip(wl.cols, 0, wl.n_elem - 1)      # rows with bad ids are excluded by callers
+    full = np.maximum.reduceat(el[cols], starts)
     full[sizes == 0] = 0.0
     return full if elems is None else full[elems]
 

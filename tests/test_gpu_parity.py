@@ -73,6 +73,9 @@ def check_workload(kbl, wl, elems=None, r_fac=None, tol=TOL):
             - wl.target.reshape(wl.dim + 2, wl.n_elem, wl.n_s).min(2))[:, sel]
     rel_span = (span / np.where(scale > 0, scale, 1)).max(0)
     assert np.all(np.abs(al[0, sel] - ral[0]) * rel_span <= 10 * tol)
+    print(f"[parity] {wl.name}: bounds err {err:.2e}, limited err {lerr:.2e}, "
+          f"limited elements {(ral[0] < 1).sum()}/{len(sel)}, p-steps {((rls & 0x10) > 0).sum()}",
+          flush=True)
     return err, lerr
 
 
