@@ -7,7 +7,7 @@ loudly if it has not been built.
 """
 
 from ._lib import (  # noqa: F401
-    GRID_GLOBAL, GRID_STENCIL, PREC_FP64, PREC_MIXED_BF16, PREC_MIXED_FP16,
+    GRID_GLOBAL, GRID_STENCIL, PREC_FP64, PREC_MIXED_BF16, PREC_MIXED_FP16, PREC_MIXED_FP32,
     ST_INADMISSIBLE, ST_RHO_FLOOR, ST_EPS_RULE, ST_LIMITED, ST_PSTEP, ST_PMEAN_FLOOR,
     ST_MEAN_OUTSIDE, ST_BAD_BOUNDS, ST_BAD_STENCIL, KblError, LIB_PATH,
 )

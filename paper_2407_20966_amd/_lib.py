@@ -24,6 +24,7 @@ GRID_STENCIL = 1
 PREC_FP64 = 0
 PREC_MIXED_BF16 = 1
 PREC_MIXED_FP16 = 2
+PREC_MIXED_FP32 = 3
 
 ST_INADMISSIBLE = 0x1
 ST_RHO_FLOOR = 0x2

@@ -72,7 +72,11 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
     if (n_elem > 0 && (!states || !rowptr || !bounds)) return KBL_ERR_ARG;
     if (nnz > 0 && !cols) return KBL_ERR_ARG;
     if (n_elem > INT64_MAX / n_s) return KBL_ERR_ARG;
-    if (params->precision != KBL_PREC_FP64) return KBL_ERR_UNSUPPORTED;
+    const int prec = params->precision;
+    if (prec != KBL_PREC_FP64 && prec != KBL_PREC_MIXED_BF16 && prec != KBL_PREC_MIXED_FP16 &&
+        prec != KBL_PREC_MIXED_FP32)
+        return KBL_ERR_UNSUPPORTED;
+    if (prec != KBL_PREC_FP64 && dim != 2) return KBL_ERR_UNSUPPORTED;
 
     const kbl_vgrid g = *vgrid;
     if (g.mode != KBL_GRID_GLOBAL && g.mode != KBL_GRID_STENCIL) return KBL_ERR_GRID;
@@ -114,7 +118,9 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
         tile = atoi(env);
         if (dim == 2 && !kbl::bounds_tile_fits_2d(tile, g.n[0], g.n[1])) tile = -1;
     }
-    hipError_t err = kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream, tile);
+    hipError_t err = prec == KBL_PREC_FP64
+                         ? kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream, tile)
+                         : kbl::launch_bounds_mixed(a, prec, (hipStream_t)stream);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 

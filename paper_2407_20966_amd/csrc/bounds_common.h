@@ -1,0 +1,225 @@
+// Device helpers shared by the FP64 and mixed-precision bounds kernels:
+// state loading and admissibility, log-Maxwellian coefficients, the stencil
+// prologue (Sec. 3.9 step 1, eq. truncdomain), reductions and stores.
+// Included by translation units compiled with -fno-honor-nans: finiteness is
+// tested on bit patterns.
+#pragma once
+
+#include <math.h>
+
+#include "kbl_internal.h"
+
+namespace kbl {
+namespace {
+
+
+constexpr int kThreads = 256;
+constexpr int kWaves = kThreads / 64;
+constexpr int kMaxStates = 256;     // stencil states staged in LDS at once
+constexpr double kInf = __builtin_inf();
+constexpr float kInfF = __builtin_inff();
+
+struct Prim {
+    double rho, ux, uy, th;
+    bool ok;
+};
+
+// This translation unit is compiled with -fno-honor-nans so that the running
+// min/max of the hot loop need no NaN canonicalisation; finiteness is
+// therefore tested on the bit pattern, which that flag cannot fold away.
+__device__ __forceinline__ bool finite_bits(double x) {
+    return (__double_as_longlong(x) & 0x7ff0000000000000LL) != 0x7ff0000000000000LL;
+}
+
+template <int D>
+__device__ __forceinline__ Prim load_prim(const BoundsArgs& p, int64_t node) {
+    Prim s;
+    const double rho = p.states[node];
+    const double mx = p.states[p.n_nodes + node];
+    const double my = (D == 2) ? p.states[2 * p.n_nodes + node] : 0.0;
+    const double E = p.states[(D + 1) * p.n_nodes + node];
+    const double mm = (D == 2) ? mx * mx + my * my : mx * mx;
+    const double P = p.gm1 * (E - 0.5 * mm / rho);
+    s.rho = rho;
+    s.ux = mx / rho;
+    s.uy = (D == 2) ? my / rho : 0.0;
+    s.th = P / rho;
+    s.ok = finite_bits(rho) && finite_bits(mx) && finite_bits(my) && finite_bits(E) &&
+           finite_bits(P) && finite_bits(s.th) && rho > 0.0 && P > 0.0;
+    return s;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Shared scratch for the per-element prologue and epilogue (up to 4 waves).
+struct Red {
+    double v[kWaves][16];
+    uint32_t flags;
+};
+
+// Per-state coefficients of the log-Maxwellian (Sec. 2.2, Sec. 3.6).
+struct Coef {
+    double a;    // ln rho - (d/2) ln(2 pi theta)
+    double al;   // a + ln(theta delta / 2)   (-inf when delta == 0)
+    double ux, uy;
+    double nk;   // -1 / (2 theta)
+};
+
+template <int D>
+__device__ __forceinline__ Coef make_coef(const BoundsArgs& p, const Prim& s) {
+    Coef c;
+    c.a = log(s.rho) - (0.5 * D) * log(2.0 * kPi * s.th);
+    c.al = (p.half_delta > 0.0) ? c.a + log(s.th * p.half_delta) : -kInf;
+    c.ux = s.ux;
+    c.uy = s.uy;
+    c.nk = -0.5 / s.th;
+    return c;
+}
+
+// Stencil state s of the row starting at row0 (the caller validated the row).
+__device__ __forceinline__ int64_t state_node(const BoundsArgs& p, int64_t row0, int64_t s) {
+    const int32_t col = p.cols[row0 + s / p.n_s];
+    return (int64_t)col * p.n_s + s % p.n_s;
+}
+
+// Prologue: admissibility, velocity box, and the coefficients of the first
+// kMaxStates states staged in sC.  Returns status bits (uniform).
+// ref (optional): max over the stencil of a and of a + l, the log-peak
+// references the mixed-precision kernels shift by.
+template <int D, int NT>
+__device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t S, Red& red,
+                                     Coef* sC, double box[4], double* ref = nullptr) {
+    constexpr int NW = NT / 64;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    uint32_t bad = 0;
+    double lx = kInf, hx = -kInf, ly = kInf, hy = -kInf, ra = -kInf, rl = -kInf;
+    for (int64_t s = tid; s < S; s += NT) {
+        const int32_t col = p.cols[row0 + s / p.n_s];
+        if (col < 0 || col >= p.n_elem) { bad |= KBL_ST_BAD_STENCIL; continue; }
+        const Prim st = load_prim<D>(p, (int64_t)col * p.n_s + s % p.n_s);
+        if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
+        const Coef c = make_coef<D>(p, st);
+        if (s < kMaxStates) sC[s] = c;
+        ra = fmax(ra, c.a);
+        rl = fmax(rl, c.al);
+        if (p.grid_mode == KBL_GRID_STENCIL) {
+            const double sd = sqrt(st.th);
+            lx = fmin(lx, st.ux - p.k * sd);
+            hx = fmax(hx, st.ux + p.k * sd);
+            if (D == 2) {
+                ly = fmin(ly, st.uy - p.k * sd);
+                hy = fmax(hy, st.uy + p.k * sd);
+            }
+        }
+    }
+    if (tid == 0) red.flags = 0;
+    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    if (ref) { ra = wave_max(ra); rl = wave_max(rl); }
+    __syncthreads();
+    if (bad) atomicOr(&red.flags, bad);
+    if (lane == 0) {
+        red.v[wid][0] = lx; red.v[wid][1] = hx; red.v[wid][2] = ly; red.v[wid][3] = hy;
+        red.v[wid][4] = ra; red.v[wid][5] = rl;
+    }
+    __syncthreads();
+    if (ref) {
+        ref[0] = red.v[0][4];
+        ref[1] = red.v[0][5];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) { ref[0] = fmax(ref[0], red.v[w][4]); ref[1] = fmax(ref[1], red.v[w][5]); }
+    }
+    if (p.grid_mode == KBL_GRID_STENCIL) {
+        box[0] = red.v[0][0]; box[1] = red.v[0][1]; box[2] = red.v[0][2]; box[3] = red.v[0][3];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) {
+            box[0] = fmin(box[0], red.v[w][0]); box[1] = fmax(box[1], red.v[w][1]);
+            box[2] = fmin(box[2], red.v[w][2]); box[3] = fmax(box[3], red.v[w][3]);
+        }
+    } else {
+        box[0] = p.lo0; box[1] = p.hi0; box[2] = p.lo1; box[3] = p.hi1;
+    }
+    const uint32_t flags = red.flags;
+    __syncthreads();   // red is reused by the caller
+    return flags;
+}
+
+// Stage the coefficients of states [c0, c0 + cn) into sC (chunks after the
+// first, for stencils larger than kMaxStates).  Bracketed by barriers.
+template <int D, int NT>
+__device__ __forceinline__ void stage_chunk(const BoundsArgs& p, int64_t row0, int64_t c0, int cn,
+                                            Coef* sC) {
+    __syncthreads();
+    for (int s = threadIdx.x; s < cn; s += NT)
+        sC[s] = make_coef<D>(p, load_prim<D>(p, state_node(p, row0, c0 + s)));
+    __syncthreads();
+}
+
+template <int D>
+__device__ __forceinline__ void store_bounds(const BoundsArgs& p, int64_t e, const double* sums,
+                                             uint32_t flags) {
+    // sums: rho_min, rho_max, E_min, E_max, then (m_min, m_max) per direction
+    const int nv = D + 2;
+    double rmin = sums[0];
+    if (rmin < p.rho_floor) { rmin = p.rho_floor; flags |= KBL_ST_RHO_FLOOR; }
+    p.bounds[0 * p.n_elem + e] = rmin;
+    p.bounds[(int64_t)nv * p.n_elem + e] = sums[1];
+    p.bounds[(int64_t)(D + 1) * p.n_elem + e] = sums[2];
+    p.bounds[(int64_t)(nv + D + 1) * p.n_elem + e] = sums[3];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+        p.bounds[(int64_t)(1 + j) * p.n_elem + e] = sums[4 + 2 * j];
+        p.bounds[(int64_t)(nv + 1 + j) * p.n_elem + e] = sums[5 + 2 * j];
+    }
+    if (p.status) p.status[e] = flags;
+}
+
+template <int D>
+__device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32_t flags) {
+    const double nan = __builtin_nan("");
+    for (int v = 0; v < 2 * (D + 2); ++v) p.bounds[(int64_t)v * p.n_elem + e] = nan;
+    if (p.status) p.status[e] = flags;
+}
+
+// Fixed-order workgroup sum of NV partials; result valid in thread 0.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum(double* part, Red& red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) part[i] = wave_sum(part[i]);
+    if (NW > 1) {
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) red.v[wid][i] = part[i];
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                double s = red.v[0][i];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) s += red.v[w][i];
+                part[i] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+}  // namespace kbl

@@ -132,6 +132,11 @@ def test_bounds_rejects_bad_grid(lib, gkw, expect):
     assert _bounds(lib, _params(lib), _grid(**gkw)) == expect
 
 
+def test_mixed_precision_is_2d_only(lib):
+    for prec in (L.PREC_MIXED_BF16, L.PREC_MIXED_FP16, L.PREC_MIXED_FP32):
+        assert _bounds(lib, _params(lib, precision=prec), _grid(n=(64, 2)), dim=1) == L.KBL_ERR_UNSUPPORTED
+
+
 def test_bounds_1d_grid_limit(lib):
     g = _grid(n=(4097, 2))
     assert _bounds(lib, _params(lib), g, dim=1) == L.KBL_ERR_GRID

@@ -1,0 +1,142 @@
+"""Mixed-precision bounds (FP32 envelopes; BF16/FP16 MFMA or FP32 VALU
+contraction) against the FP64 oracle and the FP64 GPU path.
+
+Tolerance: 1e-5 relative (density/energy against |ref|, momentum against
+the element momentum scale), and every bound must keep rho_min > 0 and
+E_min > 0.  Per-variable errors are printed for the record.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec
+from tests._parity import bounds_error, element_value_scale, limited_error, stencil_momentum_scale
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-5
+PRECS = {"fp32": 3, "fp16": 2, "bf16": 1}
+
+
+@pytest.fixture(scope="module")
+def kbl():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2407_20966_amd as kbl
+    return kbl
+
+
+def gpu_bounds(kbl, wl, precision):
+    dev = torch.device("cuda:0")
+    st = torch.from_numpy(wl.states).to(dev)
+    rp = torch.from_numpy(wl.rowptr).to(dev)
+    cl = torch.from_numpy(wl.cols).to(dev)
+    g = wl.grid
+    vg = kbl.make_vgrid(g.mode, g.n[: wl.dim], g.lo, g.hi, g.k)
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=precision)
+    b, s = kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm)
+    torch.cuda.synchronize()
+    return b.cpu().numpy(), s.cpu().numpy().view(np.uint32)
+
+
+def per_variable(err, dim):
+    nv = dim + 2
+    names = ["rho"] + [f"m{j}" for j in range(dim)] + ["E"]
+    out = {}
+    for v in range(nv):
+        out[names[v]] = float(max(err[v].max(), err[nv + v].max())) if err.size else 0.0
+    return out
+
+
+def check(kbl, wl, prec, elems=None):
+    b, s = gpu_bounds(kbl, wl, PRECS[prec])
+    sel = np.arange(wl.n_elem) if elems is None else elems
+    rb, rs = oracle.workload_bounds(wl, elems=elems)
+    mscale = stencil_momentum_scale(wl, sel)
+    err, emat = bounds_error(b[:, sel], rb, wl.dim, mscale)
+    pv = per_variable(emat, wl.dim)
+    print(f"[mixed] {wl.name} {prec}: max err {err:.2e} per variable "
+          + ", ".join(f"{k} {v:.1e}" for k, v in pv.items()), flush=True)
+    assert err <= TOL, f"{prec} bounds error {err:.3e}"
+    assert np.array_equal(s[sel] & ~np.uint32(0x2), rs & ~np.uint32(0x2))
+    good = ~np.isnan(b).any(0)
+    assert np.all(b[0, good] > 0) and np.all(b[wl.dim + 1, good] > 0)
+    return b
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("n", [(16, 16), (13, 29), (32, 32), (48, 48), (40, 64), (64, 64)])
+def test_mixed_small_stencil_box(kbl, prec, n):
+    wl = synth.make_quad_workload(N=8, seed=200 + n[0] + n[1], grid_nodes=n[0], name=f"mq_{n}")
+    wl.grid = GridSpec(GRID_STENCIL, n, k=4.0)
+    check(kbl, wl, prec)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_mixed_global_box(kbl, prec):
+    wl = synth.make_quad_workload(N=12, seed=78, field_kind="sine", grid_nodes=64,
+                                  grid_mode=GRID_GLOBAL, name="mq_sine_global")
+    check(kbl, wl, prec)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+def test_mixed_quad1024_sine_sampled(kbl, prec):
+    wl = synth.make_workload("quad1024_sine")
+    check(kbl, wl, prec, elems=synth.sample_elements(wl, 96))
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_mixed_quad256_sampled(kbl, prec):
+    wl = synth.make_workload("quad256")
+    check(kbl, wl, prec, elems=synth.sample_elements(wl, 192))
+
+
+def test_mixed_tri2m_sampled(kbl):
+    wl = synth.make_workload("tri2m")
+    check(kbl, wl, "fp16", elems=synth.sample_elements(wl, 160))
+
+
+@pytest.mark.parametrize("name", ["quad256", "quad1024_sine"])
+def test_mixed_full_vs_fp64_gpu(kbl, name):
+    """All elements: mixed vs the FP64 GPU path (itself 1e-12 of the oracle)."""
+    wl = synth.make_workload(name)
+    b64, _ = gpu_bounds(kbl, wl, 0)
+    mscale = stencil_momentum_scale(wl)
+    for prec in PRECS:
+        b, _ = gpu_bounds(kbl, wl, PRECS[prec])
+        err, emat = bounds_error(b, b64, 2, mscale)
+        pv = per_variable(emat, 2)
+        print(f"[mixed-full] {name} {prec}: max err {err:.2e} per variable "
+              + ", ".join(f"{k} {v:.1e}" for k, v in pv.items()), flush=True)
+        assert err <= TOL
+        assert np.all(b[0] > 0) and np.all(b[3] > 0)
+
+
+def test_mixed_limiter_end_to_end(kbl):
+    """Bounds from the mixed path feed the FP64 limiter; report the limited-node
+    difference against the FP64 chain."""
+    wl = synth.make_quad_workload(N=32, seed=55, grid_nodes=48, name="mq_lim")
+    dev = torch.device("cuda:0")
+    tg = torch.from_numpy(wl.target).to(dev)
+    prm = kbl.make_params(wl.gamma)
+    out = {}
+    for prec in (0, 2):
+        b, _ = gpu_bounds(kbl, wl, prec)
+        lim, al, _ = kbl.limit(tg, torch.from_numpy(b).to(dev), wl.node_weights, wl.n_s, prm)
+        torch.cuda.synchronize()
+        out[prec] = lim.cpu().numpy()
+    scale = element_value_scale(wl, wl.target)
+    lerr, _ = limited_error(out[2], out[0], scale, wl.n_s)
+    print(f"[mixed] limited nodes, fp16 bounds vs fp64 bounds: {lerr:.2e}", flush=True)
+    assert lerr <= TOL
+
+
+def test_mixed_determinism(kbl):
+    wl = synth.make_quad_workload(N=16, seed=23, grid_nodes=64, name="mq_det")
+    for prec in PRECS.values():
+        a, _ = gpu_bounds(kbl, wl, prec)
+        b, _ = gpu_bounds(kbl, wl, prec)
+        assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
