@@ -89,6 +89,7 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="quad256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args(argv)
@@ -175,6 +176,43 @@ def main(argv=None):
                       "velocity_grid": list(g.n[: wl.dim]), "precision": "fp64",
                       "parity_tol": 1e-12},
            "roofline": roof}
+    # the same step with the mixed-precision bounds (the limiter stays FP64)
+    if wl.dim == 2 and not args.no_mixed:
+        mixed = {}
+        for name, prec in (("fp32_valu", kbl.PREC_MIXED_FP32), ("fp16_mfma", kbl.PREC_MIXED_FP16),
+                           ("bf16_mfma", kbl.PREC_MIXED_BF16)):
+            prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=prec)
+
+            def mstep(ev=None):
+                if ev is not None:
+                    ev[0].record(stream)
+                kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm_m, out=bounds, status=bstat,
+                                   stream=stream)
+                if ev is not None:
+                    ev[1].record(stream)
+                kbl.limit(tg, bounds, wl.node_weights, wl.n_s, prm, out=lim, alpha=alpha,
+                          status=lstat, stream=stream)
+                if ev is not None:
+                    ev[2].record(stream)
+
+            for _ in range(args.warmup):
+                mstep()
+            torch.cuda.synchronize()
+            mev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                   for _ in range(args.steps)]
+            t0 = time.perf_counter()
+            for i in range(args.steps):
+                mstep(mev[i])
+            torch.cuda.synchronize()
+            mwall = (time.perf_counter() - t0) / args.steps
+            mb = float(np.mean([e[0].elapsed_time(e[1]) for e in mev]))
+            mixed[name] = {"value": wl.n_elem / mwall, "unit": "elements/s",
+                           "ms_per_step": 1e3 * mwall, "bounds_ms": mb,
+                           "frac": ops / (mb * 1e-3) / VALU_PEAK_OPS,
+                           "speedup_vs_fp64": ms_step / (1e3 * mwall), "parity_tol": 1e-5}
+            print(f"[bench] mixed {name}: {1e3 * mwall:.3f} ms/step (bounds {mb:.3f} ms)",
+                  file=sys.stderr, flush=True)
+        out["mixed"] = mixed
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -38,6 +38,7 @@ typedef float float4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kTab = 64;            // states per FP32 coefficient / B-table chunk
 constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kF16Scale = 16384.0f;            // 2^14, exact
 
 struct CoefF {
     float a;    // a - ref_T
@@ -64,10 +65,12 @@ __device__ __forceinline__ float4_t mfma_ystage(const float* f, const float* yb)
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         if (CT == KBL_PREC_MIXED_FP16) {
+            // both operands are scaled by 2^14 (envelopes <= 1, factors < 2)
+            // so that the low halves stay clear of FP16 subnormals
             half4_t ah, al, bh, bl;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float av = f[4 * k + i], bv = yb[4 * k + i];
+                const float av = f[4 * k + i] * kF16Scale, bv = yb[4 * k + i] * kF16Scale;
                 ah[i] = (_Float16)av;
                 al[i] = (_Float16)(av - (float)ah[i]);
                 bh[i] = (_Float16)bv;
@@ -110,7 +113,7 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
     constexpr int TY = 4 * KS;      // y nodes per lane
     __shared__ Coef sC[kMaxStates];
     __shared__ CoefF sF[kTab];
-    __shared__ float sB[kTab][NY];
+    __shared__ __align__(16) float sB[kTab][NY];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
@@ -286,7 +289,8 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
             const float4_t c_tx = mfma_ystage<KS, CT>(tX, yb);
             const float4_t c_in = mfma_ystage<KS, CT>(in_, yb);
             const float4_t c_ix = mfma_ystage<KS, CT>(iX, yb);
-            const double unscale = 1.0 / yscale;
+            const double unscale =
+                (CT == KBL_PREC_MIXED_FP16 ? 1.0 / ((double)kF16Scale * kF16Scale) : 1.0) / yscale;
             // x stage: lane holds factor xr at x rows 16w + 4g + i
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
