@@ -60,7 +60,7 @@ typedef enum {
 #define KBL_PREC_MIXED_FP16  2   /* FP32 envelopes/exp, FP16 MFMA contraction (hi/lo split) */
 #define KBL_PREC_MIXED_FP32  3   /* FP32 envelopes/exp, FP32 VALU contraction */
 
-/* Per-element status bits.  kbl_compute_bounds writes bits 0x1-0x2 and 0x100;
+/* Per-element status bits.  kbl_compute_bounds writes bits 0x1-0x2 and 0x100-0x200;
  * kbl_limit writes bits 0x4-0x80. */
 #define KBL_ST_INADMISSIBLE  0x1u    /* a stencil state has rho<=0, P<=0 or a non-finite value: bounds are NaN */
 #define KBL_ST_RHO_FLOOR     0x2u    /* rho_min was raised to rho_floor (Sec. 3.8) */
@@ -71,6 +71,7 @@ typedef enum {
 #define KBL_ST_MEAN_OUTSIDE  0x40u   /* element mean lies outside its bounds */
 #define KBL_ST_BAD_BOUNDS    0x80u   /* bounds not finite: element passed through unchanged */
 #define KBL_ST_BAD_STENCIL   0x100u  /* stencil row out of range (rowptr or cols): bounds are NaN */
+#define KBL_ST_TOO_LARGE     0x200u  /* mixed precision only: more than 256 stencil states, bounds are NaN */
 
 typedef struct {
     int32_t mode;       /* KBL_GRID_GLOBAL or KBL_GRID_STENCIL */

@@ -35,6 +35,7 @@ ST_PMEAN_FLOOR = 0x20
 ST_MEAN_OUTSIDE = 0x40
 ST_BAD_BOUNDS = 0x80
 ST_BAD_STENCIL = 0x100
+ST_TOO_LARGE = 0x200
 
 
 class VGrid(C.Structure):

@@ -112,15 +112,16 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
     a.half_delta = half_delta;
     a.r_fac = params->r_fac;
     a.rho_floor = params->rho_floor;
-    // KBL_BOUNDS_TILE (tuning knob) forces a 2D tile configuration index
+    // KBL_BOUNDS_TILE / KBL_MIXED_TILE (tuning knobs) force a tile configuration
     int tile = -1;
-    if (const char* env = getenv("KBL_BOUNDS_TILE")) {
+    if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE")) {
         tile = atoi(env);
-        if (dim == 2 && !kbl::bounds_tile_fits_2d(tile, g.n[0], g.n[1])) tile = -1;
+        if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, g.n[0], g.n[1]))
+            tile = -1;
     }
     hipError_t err = prec == KBL_PREC_FP64
                          ? kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream, tile)
-                         : kbl::launch_bounds_mixed(a, prec, (hipStream_t)stream);
+                         : kbl::launch_bounds_mixed(a, prec, (hipStream_t)stream, tile);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 

@@ -96,8 +96,9 @@ __device__ __forceinline__ int64_t state_node(const BoundsArgs& p, int64_t row0,
     return (int64_t)col * p.n_s + s % p.n_s;
 }
 
-// Prologue: admissibility, velocity box, and the coefficients of the first
-// kMaxStates states staged in sC.  Returns status bits (uniform).
+// Prologue: admissibility, velocity box, and (if sC is given) the
+// coefficients of the first kMaxStates states staged in sC.  Returns status
+// bits (uniform).
 // ref (optional): max over the stencil of a and of a + l, the log-peak
 // references the mixed-precision kernels shift by.
 template <int D, int NT>
@@ -114,7 +115,7 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t 
         const Prim st = load_prim<D>(p, (int64_t)col * p.n_s + s % p.n_s);
         if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
         const Coef c = make_coef<D>(p, st);
-        if (s < kMaxStates) sC[s] = c;
+        if (sC && s < kMaxStates) sC[s] = c;
         ra = fmax(ra, c.a);
         rl = fmax(rl, c.al);
         if (p.grid_mode == KBL_GRID_STENCIL) {

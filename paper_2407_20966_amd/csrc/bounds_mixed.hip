@@ -20,13 +20,14 @@
 //    split in three, FP32 accumulation) or on the FP32 VALU; the x stage and
 //    everything after it is FP64.
 //
-// Workgroup = NW waves; wave w owns x nodes 16w..16w+15.  Lane l of a wave
-// owns x node 16w + l%16 and the y nodes 16k + 4(l/16) + i (i < 4, k < KS):
-// exactly the A-operand layout of the 16x16x16 MFMA with M = x, K = y, so the
-// envelope values feed the matrix core straight from registers.  The B
-// operand (lane l: factor l%16 at the same y nodes) is built per element in
-// registers; the C result (lane l: factor l%16 at x rows 16w + 4(l/16) + i)
-// is contracted with X in FP64.
+// Workgroup = NW waves; the x nodes come in tiles of 16 and a wave owns TXW
+// of them.  Lane l owns x node 16t + l%16 of each of its tiles t and the y
+// nodes 16k + 4(l/16) + i (i < 4, k < KS): per tile, exactly the A-operand
+// layout of the 16x16x16 MFMA with M = x, K = y, so the envelope values feed
+// the matrix core straight from registers.  The B operand (lane l: factor
+// l%16 at the same y nodes) is built per element in registers; the C result
+// (lane l: factor l%16 at x rows 16t + 4(l/16) + i) is contracted with X in
+// FP64.  One B-table read serves the TXW x nodes of a lane.
 #include "bounds_common.h"
 
 namespace kbl {
@@ -36,7 +37,12 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kTab = 64;            // states per FP32 coefficient / B-table chunk
+constexpr int kTab = 64;            // states per B-table chunk
+
+// Minimum waves per SIMD the register allocator targets (1 = no constraint).
+#ifndef KBL_MIXED_WAVES
+#define KBL_MIXED_WAVES 1
+#endif
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kF16Scale = 16384.0f;            // 2^14, exact
 
@@ -57,8 +63,8 @@ __device__ __forceinline__ float bf2f(short b) {
     return __uint_as_float(((uint32_t)(uint16_t)b) << 16);
 }
 
-// y-stage contraction of one envelope on MFMA: returns C (lane l: factor
-// l%16 at x rows 4(l/16) + i of the wave's 16 rows).
+// y-stage contraction of one envelope (one x tile) on MFMA: returns C
+// (lane l: factor l%16 at x rows 4(l/16) + i of the tile).
 template <int KS, int CT>
 __device__ __forceinline__ float4_t mfma_ystage(const float* f, const float* yb) {
     float4_t acc = {0.f, 0.f, 0.f, 0.f};
@@ -102,23 +108,46 @@ __device__ __forceinline__ float4_t mfma_ystage(const float* f, const float* yb)
     return acc;
 }
 
-// Partial sums per envelope, in this order: T_min: S0, SXm, SXp, SYm, SYp, S2;
-// T_max: the same six; I_min: S0; I_max: S0.
+// Trapezoid weight (Sec. 3.7) times the x factors X = Wx {1, ux<0, ux>=0, ux^2}.
+struct XF {
+    double w, m, p, q;
+};
+__device__ __forceinline__ XF x_factors(const BoundsArgs& p, const double* box, double hx, int x) {
+    XF f = {0.0, 0.0, 0.0, 0.0};
+    if (x < p.nx) {
+        const double u = box[0] + x * hx;
+        f.w = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
+        f.m = u < 0.0 ? f.w * u : 0.0;
+        f.p = u < 0.0 ? 0.0 : f.w * u;
+        f.q = f.w * u * u;
+    }
+    return f;
+}
+
+// Partial sums, in this order: T_min: S0, SXm, SXp, SYm, SYp, S2; T_max: the
+// same six; I_min: S0; I_max: S0.
 constexpr int kNP = 14;
 
-template <int NW, int KS, int CT>
-__global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
+// NW waves; wave w owns the x tiles w + NW i (i < TXW) of 16 nodes each; lane
+// l owns x node 16 t + l%16 of each of its tiles and the y nodes
+// 16 k + 4 (l/16) + i (i < 4, k < KS).
+template <int TXW, int KS, int NW, int CT>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIXED_WAVES))) void bounds_mixed_2d(BoundsArgs p) {
     constexpr int NT = NW * 64;
     constexpr int NY = 16 * KS;     // y nodes covered
     constexpr int TY = 4 * KS;      // y nodes per lane
-    __shared__ Coef sC[kMaxStates];
-    __shared__ CoefF sF[kTab];
-    __shared__ __align__(16) float sB[kTab][NY];
+    // the FP64 coefficients are only needed until the FP32 copies exist; the
+    // B table reuses their space
+    union Stage {
+        Coef c[kMaxStates];
+        float b[kTab][NY];
+    };
+    __shared__ __align__(16) Stage stage;
+    __shared__ CoefF sF[kMaxStates];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, xr = l & 15, g = l >> 4;
-    const int tx = 16 * w + xr;
 
     for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
@@ -127,8 +156,14 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
             continue;
         }
         const int64_t S = (row1 - row0) * p.n_s;
+        if (S > kMaxStates) {
+            // the mixed path keeps every stencil state in LDS
+            if (tid == 0) store_nan<2>(p, e, KBL_ST_TOO_LARGE);
+            continue;
+        }
         double box[4], ref[2];
-        const uint32_t flags = stencil_prologue<2, NT>(p, row0, S, red, sC, box, ref);
+        __syncthreads();   // the previous element's B table is no longer read
+        const uint32_t flags = stencil_prologue<2, NT>(p, row0, S, red, stage.c, box, ref);
         if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
             if (tid == 0) store_nan<2>(p, e, flags);
             continue;
@@ -138,88 +173,93 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
         const double hy = (box[3] - box[2]) / (double)(p.ny - 1);
         const double cx = box[0] + 0.5 * (box[1] - box[0]);
         const double cy = box[2] + 0.5 * (box[3] - box[2]);
-
-        // centred node coordinates of this lane (clamped for the ragged tail)
-        const float uxc = (float)((box[0] + (tx < p.nx ? tx : p.nx - 1) * hx) - cx);
-        float tn[TY], tX[TY], in_[TY], iX[TY];
-#pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            tn[j] = kInfF; tX[j] = -kInfF; in_[j] = kInfF; iX[j] = -kInfF;
+        const int ns = (int)S;
+        // shifted, centred FP32 coefficients of every state
+        for (int s = tid; s < ns; s += NT) {
+            const Coef c = stage.c[s];
+            CoefF f;
+            f.a = (float)(c.a - ref[0]);
+            f.al = has_i ? (float)(c.al - ref[1]) : -kInfF;
+            f.ux = (float)(c.ux - cx);
+            f.uy = (float)(c.uy - cy);
+            f.nk = (float)c.nk;
+            sF[s] = f;
         }
 
-        for (int64_t c0 = 0; c0 < S; c0 += kTab) {
-            const int cn = (int)((S - c0) < kTab ? (S - c0) : kTab);
-            __syncthreads();
-            for (int s = tid; s < cn; s += NT) {
-                const int64_t gs = c0 + s;
-                const Coef c = gs < kMaxStates ? sC[gs]
-                                               : make_coef<2>(p, load_prim<2>(p, state_node(p, row0, gs)));
-                CoefF f;
-                f.a = (float)(c.a - ref[0]);
-                f.al = has_i ? (float)(c.al - ref[1]) : -kInfF;
-                f.ux = (float)(c.ux - cx);
-                f.uy = (float)(c.uy - cy);
-                f.nk = (float)c.nk;
-                sF[s] = f;
+        // centred x coordinates of this lane's nodes (clamped for the ragged tail)
+        float uxc[TXW];
+#pragma unroll
+        for (int i = 0; i < TXW; ++i) {
+            const int x = 16 * (w + NW * i) + xr;
+            uxc[i] = (float)((box[0] + (x < p.nx ? x : p.nx - 1) * hx) - cx);
+        }
+        float tn[TXW][TY], tX[TXW][TY], in_[TXW][TY], iX[TXW][TY];
+#pragma unroll
+        for (int i = 0; i < TXW; ++i)
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                tn[i][j] = kInfF; tX[i][j] = -kInfF; in_[i][j] = kInfF; iX[i][j] = -kInfF;
             }
+
+        for (int c0 = 0; c0 < ns; c0 += kTab) {
+            const int cn = (ns - c0) < kTab ? (ns - c0) : kTab;
             __syncthreads();
             for (int idx = tid; idx < cn * NY; idx += NT) {
                 const int s = idx / NY, j = idx - s * NY;
                 const float uyc = (float)((box[2] + (j < p.ny ? j : p.ny - 1) * hy) - cy);
-                const float d = uyc - sF[s].uy;
-                sB[s][j] = (sF[s].nk * d) * d;
+                const float d = uyc - sF[c0 + s].uy;
+                stage.b[s][j] = (sF[c0 + s].nk * d) * d;
             }
             __syncthreads();
             int s = 0;
             for (; s + 1 < cn; s += 2) {
-                const CoefF c1 = sF[s], c2 = sF[s + 1];
-                const float d1 = uxc - c1.ux, t1 = c1.nk * d1;
-                const float d2 = uxc - c2.ux, t2 = c2.nk * d2;
-                const float A1 = fmaf(t1, d1, c1.a), I1 = fmaf(t1, d1, c1.al);
-                const float A2 = fmaf(t2, d2, c2.a), I2 = fmaf(t2, d2, c2.al);
+                const CoefF c1 = sF[c0 + s], c2 = sF[c0 + s + 1];
+                float A1[TXW], I1[TXW], A2[TXW], I2[TXW];
+#pragma unroll
+                for (int i = 0; i < TXW; ++i) {
+                    const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
+                    const float d2 = uxc[i] - c2.ux, t2 = c2.nk * d2;
+                    A1[i] = fmaf(t1, d1, c1.a); I1[i] = fmaf(t1, d1, c1.al);
+                    A2[i] = fmaf(t2, d2, c2.a); I2[i] = fmaf(t2, d2, c2.al);
+                }
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
-                    const float4_t b1 = *reinterpret_cast<const float4_t*>(&sB[s][16 * k + 4 * g]);
-                    const float4_t b2 = *reinterpret_cast<const float4_t*>(&sB[s + 1][16 * k + 4 * g]);
+                    const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.b[s][16 * k + 4 * g]);
+                    const float4_t b2 = *reinterpret_cast<const float4_t*>(&stage.b[s + 1][16 * k + 4 * g]);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int j = 4 * k + i;
-                        const float q1 = A1 + b1[i], q2 = A2 + b2[i];
-                        const float r1 = I1 + b1[i], r2 = I2 + b2[i];
-                        tn[j] = fminf(tn[j], fminf(q1, q2));
-                        tX[j] = fmaxf(tX[j], fmaxf(q1, q2));
-                        in_[j] = fminf(in_[j], fminf(r1, r2));
-                        iX[j] = fmaxf(iX[j], fmaxf(r1, r2));
-                    }
+                    for (int i = 0; i < TXW; ++i)
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const int j = 4 * k + m;
+                            const float q1 = A1[i] + b1[m], q2 = A2[i] + b2[m];
+                            const float r1 = I1[i] + b1[m], r2 = I2[i] + b2[m];
+                            tn[i][j] = fminf(tn[i][j], fminf(q1, q2));
+                            tX[i][j] = fmaxf(tX[i][j], fmaxf(q1, q2));
+                            in_[i][j] = fminf(in_[i][j], fminf(r1, r2));
+                            iX[i][j] = fmaxf(iX[i][j], fmaxf(r1, r2));
+                        }
                 }
             }
             if (s < cn) {
-                const CoefF c1 = sF[s];
-                const float d1 = uxc - c1.ux, t1 = c1.nk * d1;
-                const float A1 = fmaf(t1, d1, c1.a), I1 = fmaf(t1, d1, c1.al);
+                const CoefF c1 = sF[c0 + s];
 #pragma unroll
-                for (int k = 0; k < KS; ++k) {
-                    const float4_t b1 = *reinterpret_cast<const float4_t*>(&sB[s][16 * k + 4 * g]);
+                for (int i = 0; i < TXW; ++i) {
+                    const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
+                    const float A1 = fmaf(t1, d1, c1.a), I1 = fmaf(t1, d1, c1.al);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int j = 4 * k + i;
-                        const float q1 = A1 + b1[i], r1 = I1 + b1[i];
-                        tn[j] = fminf(tn[j], q1);
-                        tX[j] = fmaxf(tX[j], q1);
-                        in_[j] = fminf(in_[j], r1);
-                        iX[j] = fmaxf(iX[j], r1);
+                    for (int k = 0; k < KS; ++k) {
+                        const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.b[s][16 * k + 4 * g]);
+#pragma unroll
+                        for (int m = 0; m < 4; ++m) {
+                            const int j = 4 * k + m;
+                            tn[i][j] = fminf(tn[i][j], A1 + b1[m]);
+                            tX[i][j] = fmaxf(tX[i][j], A1 + b1[m]);
+                            in_[i][j] = fminf(in_[i][j], I1 + b1[m]);
+                            iX[i][j] = fmaxf(iX[i][j], I1 + b1[m]);
+                        }
                     }
                 }
             }
-        }
-
-        // envelope values exp(q - ref) in (0, 1]
-#pragma unroll
-        for (int j = 0; j < TY; ++j) {
-            tn[j] = __builtin_amdgcn_exp2f(tn[j] * kLog2e);
-            tX[j] = __builtin_amdgcn_exp2f(tX[j] * kLog2e);
-            in_[j] = __builtin_amdgcn_exp2f(in_[j] * kLog2e);
-            iX[j] = __builtin_amdgcn_exp2f(iX[j] * kLog2e);
         }
 
         double part[kNP];
@@ -227,91 +267,105 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
         for (int i = 0; i < kNP; ++i) part[i] = 0.0;
 
         if (CT == KBL_PREC_MIXED_FP32) {
-            // y stage on the VALU (FP32) for this lane's single x node
-            float H[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, HI[2] = {0, 0};
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                const int ty = 16 * (j / 4) + 4 * g + (j % 4);
-                if (ty >= p.ny) continue;
-                const double uyd = box[2] + ty * hy;
-                const double wy = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
-                const float y0 = (float)wy;
-                const float y1 = (float)(uyd < 0.0 ? wy * uyd : 0.0);
-                const float y2 = (float)(uyd < 0.0 ? 0.0 : wy * uyd);
-                const float y3 = (float)(wy * uyd * uyd);
-                H[0][0] = fmaf(tn[j], y0, H[0][0]); H[0][1] = fmaf(tn[j], y1, H[0][1]);
-                H[0][2] = fmaf(tn[j], y2, H[0][2]); H[0][3] = fmaf(tn[j], y3, H[0][3]);
-                H[1][0] = fmaf(tX[j], y0, H[1][0]); H[1][1] = fmaf(tX[j], y1, H[1][1]);
-                H[1][2] = fmaf(tX[j], y2, H[1][2]); H[1][3] = fmaf(tX[j], y3, H[1][3]);
-                HI[0] = fmaf(in_[j], y0, HI[0]);
-                HI[1] = fmaf(iX[j], y0, HI[1]);
-            }
-            if (tx < p.nx) {
-                const double uxd = box[0] + tx * hx;
-                const double wx = hx * ((tx == 0 || tx == p.nx - 1) ? 0.5 : 1.0);
-                const double x1 = uxd < 0.0 ? wx * uxd : 0.0, x2 = uxd < 0.0 ? 0.0 : wx * uxd;
-                const double x3 = wx * uxd * uxd;
+            for (int i = 0; i < TXW; ++i) {
+                // y stage on the VALU (FP32), then the x stage in FP64
+                float H[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, HI[2] = {0, 0};
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const int ty = 16 * (j / 4) + 4 * g + (j % 4);
+                    float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f;
+                    if (ty < p.ny) {
+                        const double u = box[2] + ty * hy;
+                        const double a0 = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
+                        y0 = (float)a0;
+                        y1 = (float)(u < 0.0 ? a0 * u : 0.0);
+                        y2 = (float)(u < 0.0 ? 0.0 : a0 * u);
+                        y3 = (float)(a0 * u * u);
+                    }
+                    const float fa = __builtin_amdgcn_exp2f(tn[i][j] * kLog2e);
+                    const float fb = __builtin_amdgcn_exp2f(tX[i][j] * kLog2e);
+                    H[0][0] = fmaf(fa, y0, H[0][0]); H[0][1] = fmaf(fa, y1, H[0][1]);
+                    H[0][2] = fmaf(fa, y2, H[0][2]); H[0][3] = fmaf(fa, y3, H[0][3]);
+                    H[1][0] = fmaf(fb, y0, H[1][0]); H[1][1] = fmaf(fb, y1, H[1][1]);
+                    H[1][2] = fmaf(fb, y2, H[1][2]); H[1][3] = fmaf(fb, y3, H[1][3]);
+                    HI[0] = fmaf(__builtin_amdgcn_exp2f(in_[i][j] * kLog2e), y0, HI[0]);
+                    HI[1] = fmaf(__builtin_amdgcn_exp2f(iX[i][j] * kLog2e), y0, HI[1]);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const XF X = x_factors(p, box, hx, 16 * (w + NW * i) + xr);
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
-                    part[6 * v + 0] = wx * H[v][0];
-                    part[6 * v + 1] = x1 * H[v][0];
-                    part[6 * v + 2] = x2 * H[v][0];
-                    part[6 * v + 3] = wx * H[v][1];
-                    part[6 * v + 4] = wx * H[v][2];
-                    part[6 * v + 5] = 0.5 * (x3 * H[v][0] + wx * H[v][3]);
+                    part[6 * v + 0] += X.w * H[v][0];
+                    part[6 * v + 1] += X.m * H[v][0];
+                    part[6 * v + 2] += X.p * H[v][0];
+                    part[6 * v + 3] += X.w * H[v][1];
+                    part[6 * v + 4] += X.w * H[v][2];
+                    part[6 * v + 5] += 0.5 * (X.q * H[v][0] + X.w * H[v][3]);
                 }
-                part[12] = wx * HI[0];
-                part[13] = wx * HI[1];
+                part[12] += X.w * HI[0];
+                part[13] += X.w * HI[1];
             }
         } else {
             // B operand: factor n = l%16 (0..3 used) at this lane's y nodes,
-            // scaled by a power of two so that it stays well inside the
-            // FP16/BF16 range
+            // scaled by a power of two into [1, 2)
             const double umax = fmax(fabs(box[2]), fabs(box[3]));
             const double bound = xr == 0 ? hy : (xr == 3 ? hy * umax * umax : hy * umax);
             const double yscale = (xr < 4 && bound > 0.0) ? ldexp(1.0, -ilogb(bound)) : 1.0;
+            const double unscale =
+                (CT == KBL_PREC_MIXED_FP16 ? 1.0 / ((double)kF16Scale * kF16Scale) : 1.0) / yscale;
             float yb[TY];
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
                 const int ty = 16 * (j / 4) + 4 * g + (j % 4);
                 double v = 0.0;
                 if (ty < p.ny && xr < 4) {
-                    const double uyd = box[2] + ty * hy;
+                    const double u = box[2] + ty * hy;
                     const double wy = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
                     v = xr == 0 ? wy
-                      : xr == 1 ? (uyd < 0.0 ? wy * uyd : 0.0)
-                      : xr == 2 ? (uyd < 0.0 ? 0.0 : wy * uyd)
-                                : wy * uyd * uyd;
+                      : xr == 1 ? (u < 0.0 ? wy * u : 0.0)
+                      : xr == 2 ? (u < 0.0 ? 0.0 : wy * u)
+                                : wy * u * u;
                 }
                 yb[j] = (float)(v * yscale);
             }
-            const float4_t c_tn = mfma_ystage<KS, CT>(tn, yb);
-            const float4_t c_tx = mfma_ystage<KS, CT>(tX, yb);
-            const float4_t c_in = mfma_ystage<KS, CT>(in_, yb);
-            const float4_t c_ix = mfma_ystage<KS, CT>(iX, yb);
-            const double unscale =
-                (CT == KBL_PREC_MIXED_FP16 ? 1.0 / ((double)kF16Scale * kF16Scale) : 1.0) / yscale;
-            // x stage: lane holds factor xr at x rows 16w + 4g + i
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int x = 16 * w + 4 * g + i;
-                if (x >= p.nx || xr >= 4) continue;
-                const double uxd = box[0] + x * hx;
-                const double wx = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
-                const double x1 = uxd < 0.0 ? wx * uxd : 0.0, x2 = uxd < 0.0 ? 0.0 : wx * uxd;
-                const double x3 = wx * uxd * uxd;
-                const double htn = c_tn[i] * unscale, htx = c_tx[i] * unscale;
-                if (xr == 0) {
-                    part[0] += wx * htn; part[1] += x1 * htn; part[2] += x2 * htn; part[5] += 0.5 * x3 * htn;
-                    part[6] += wx * htx; part[7] += x1 * htx; part[8] += x2 * htx; part[11] += 0.5 * x3 * htx;
-                    part[12] += wx * (c_in[i] * unscale);
-                    part[13] += wx * (c_ix[i] * unscale);
-                } else if (xr == 1) {
-                    part[3] += wx * htn; part[9] += wx * htx;
-                } else if (xr == 2) {
-                    part[4] += wx * htn; part[10] += wx * htx;
-                } else {
-                    part[5] += 0.5 * wx * htn; part[11] += 0.5 * wx * htx;
+            for (int i = 0; i < TXW; ++i) {
+                // x rows of the C result held by this lane
+                XF X[4];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) X[r] = x_factors(p, box, hx, 16 * (w + NW * i) + 4 * g + r);
+#pragma unroll
+                for (int env = 0; env < 4; ++env) {
+                    float f[TY];
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        const float q = env == 0 ? tn[i][j] : env == 1 ? tX[i][j] : env == 2 ? in_[i][j] : iX[i][j];
+                        f[j] = __builtin_amdgcn_exp2f(q * kLog2e);
+                    }
+                    const float4_t c = mfma_ystage<KS, CT>(f, yb);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (xr < 4) {
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const double h = c[r] * unscale;
+                            if (env < 2) {
+                                double* pv = part + 6 * env;
+                                if (xr == 0) {
+                                    pv[0] += X[r].w * h; pv[1] += X[r].m * h; pv[2] += X[r].p * h;
+                                    pv[5] += 0.5 * X[r].q * h;
+                                } else if (xr == 1) {
+                                    pv[3] += X[r].w * h;
+                                } else if (xr == 2) {
+                                    pv[4] += X[r].w * h;
+                                } else {
+                                    pv[5] += 0.5 * X[r].w * h;
+                                }
+                            } else if (xr == 0) {
+                                part[12 + env - 2] += X[r].w * h;
+                            }
+                        }
+                    }
                 }
             }
         }
@@ -334,35 +388,62 @@ __global__ __launch_bounds__(NW * 64) void bounds_mixed_2d(BoundsArgs p) {
     }
 }
 
-template <int NW, int KS, int CT>
+template <int TXW, int KS, int NW, int CT>
 hipError_t launch_mixed(const BoundsArgs& a, hipStream_t stream) {
     const int64_t grid = a.n_elem < (int64_t)INT32_MAX ? a.n_elem : (int64_t)INT32_MAX;
-    hipLaunchKernelGGL((bounds_mixed_2d<NW, KS, CT>), dim3((unsigned)grid), dim3(NW * 64), 0,
+    hipLaunchKernelGGL((bounds_mixed_2d<TXW, KS, NW, CT>), dim3((unsigned)grid), dim3(NW * 64), 0,
                        stream, a);
     return hipGetLastError();
 }
 
-template <int CT>
-hipError_t launch_ct(const BoundsArgs& a, hipStream_t stream) {
-    const int mx = (a.nx + 15) / 16, my = (a.ny + 15) / 16;
-    const int m = mx > my ? mx : my;
-    if (m <= 1) return launch_mixed<1, 1, CT>(a, stream);
-    if (m <= 2) return launch_mixed<2, 2, CT>(a, stream);
-    if (m <= 3) return launch_mixed<3, 3, CT>(a, stream);
-    if (m <= 4) return launch_mixed<4, 4, CT>(a, stream);
-    return hipErrorInvalidValue;
+// Tile configurations (TXW, KS, NW): x tiles of 16 nodes per wave, y steps
+// of 16, waves per workgroup.  Covers nx <= 16 TXW NW, ny <= 16 KS.
+struct MixedTile {
+    int txw, ks, nw;
+    hipError_t (*fn[3])(const BoundsArgs&, hipStream_t);
+};
+#define KBL_MTILE(T, K, W) \
+    {T, K, W, {launch_mixed<T, K, W, KBL_PREC_MIXED_BF16>, launch_mixed<T, K, W, KBL_PREC_MIXED_FP16>, \
+               launch_mixed<T, K, W, KBL_PREC_MIXED_FP32>}}
+constexpr MixedTile kMixedTiles[] = {
+    KBL_MTILE(1, 1, 1),   // 0: n <= 16
+    KBL_MTILE(2, 2, 1),   // 1: n <= 32
+    KBL_MTILE(1, 2, 2),   // 2: n <= 32, two waves
+    KBL_MTILE(3, 3, 1),   // 3: n <= 48, one wave
+    KBL_MTILE(1, 3, 3),   // 4: n <= 48, three waves
+    KBL_MTILE(2, 4, 2),   // 5: n <= 64, two waves
+    KBL_MTILE(1, 4, 4),   // 6: n <= 64, four waves
+};
+#undef KBL_MTILE
+constexpr int kNumMixedTiles = sizeof(kMixedTiles) / sizeof(kMixedTiles[0]);
+
+bool mixed_tile_fits(int t, int nx, int ny) {
+    if (t < 0 || t >= kNumMixedTiles) return false;
+    const MixedTile& m = kMixedTiles[t];
+    return nx <= 16 * m.txw * m.nw && ny <= 16 * m.ks;
+}
+
+// Defaults from a measured sweep (48x48: FP32 VALU contraction prefers three
+// single-tile waves, the MFMA contraction one wave of three tiles; 64x64:
+// two waves of two tiles).
+int default_mixed_tile(int nx, int ny, int precision) {
+    const int n = nx > ny ? nx : ny;
+    if (n <= 16) return 0;
+    if (n <= 32) return 1;
+    if (n <= 48) return precision == KBL_PREC_MIXED_FP32 ? 4 : 3;
+    return 5;
 }
 
 }  // namespace
 
-hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream) {
+hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile) {
     if (a.n_elem == 0) return hipSuccess;
-    switch (precision) {
-        case KBL_PREC_MIXED_FP32: return launch_ct<KBL_PREC_MIXED_FP32>(a, stream);
-        case KBL_PREC_MIXED_FP16: return launch_ct<KBL_PREC_MIXED_FP16>(a, stream);
-        case KBL_PREC_MIXED_BF16: return launch_ct<KBL_PREC_MIXED_BF16>(a, stream);
-    }
-    return hipErrorInvalidValue;
+    if (tile < 0 || !mixed_tile_fits(tile, a.nx, a.ny)) tile = default_mixed_tile(a.nx, a.ny, precision);
+    if (!mixed_tile_fits(tile, a.nx, a.ny)) return hipErrorInvalidValue;
+    const int slot = precision == KBL_PREC_MIXED_BF16 ? 0 : precision == KBL_PREC_MIXED_FP16 ? 1
+                   : precision == KBL_PREC_MIXED_FP32 ? 2 : -1;
+    if (slot < 0) return hipErrorInvalidValue;
+    return kMixedTiles[tile].fn[slot](a, stream);
 }
 
 }  // namespace kbl

@@ -55,7 +55,8 @@ struct LimitArgs {
 hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile);
 int bounds_tile_count_2d();
 bool bounds_tile_fits_2d(int tile, int nx, int ny);
-hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream);
+// tile < 0 (or a tile that does not fit) selects the default for the grid size.
+hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
 
 }  // namespace kbl
