@@ -67,6 +67,10 @@ def _load():
         lib.oracle_limit.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                      C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P, P]
         lib.oracle_limit.restype = C.c_int
+        lib.oracle_backward.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
+                                        C.c_double, C.c_int, P, P, P, C.c_double, C.c_int64,
+                                        C.c_int, P, P, P, P, P, P, P, P, P]
+        lib.oracle_backward.restype = C.c_int
         lib.oracle_delta.argtypes = [C.c_int, C.c_double]
         lib.oracle_delta.restype = C.c_double
         _lib = lib
@@ -134,6 +138,40 @@ def limit(dim: int, gamma: float, solution: np.ndarray, bounds_sel: np.ndarray,
     if rc != 0:
         raise ValueError("oracle_limit rejected its arguments")
     return lim, al, st
+
+
+def backward(dim, gamma, states, rowptr, cols, n_s, grid_mode, n, lo, hi, k, r_fac,
+             solution, node_weights, grad_limited, rho_floor=RHO_FLOOR, p_floor=P_FLOOR,
+             eps=EPS_ALPHA):
+    """Analytic subgradient: (dJ/dsolution, dJ/dstates, dJ/dbounds) for
+    G = dJ/dlimited (all elements, serial)."""
+    lib = _load()
+    states = np.ascontiguousarray(states, dtype=np.float64)
+    solution = np.ascontiguousarray(solution, dtype=np.float64)
+    G = np.ascontiguousarray(grad_limited, dtype=np.float64)
+    rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    c = np.ascontiguousarray(node_weights, dtype=np.float64)
+    n_elem = rowptr.size - 1
+    n_arr = np.array(list(n) + [2] * (2 - len(n)), dtype=np.int32)[:2]
+    lo_arr = np.array(list(lo) + [0.0] * (2 - len(lo)), dtype=np.float64)[:2]
+    hi_arr = np.array(list(hi) + [0.0] * (2 - len(hi)), dtype=np.float64)[:2]
+    gsol = np.empty_like(solution)
+    gst = np.empty_like(states)
+    gb = np.empty((2 * (dim + 2), n_elem), dtype=np.float64)
+    rc = lib.oracle_backward(dim, gamma, r_fac, rho_floor, p_floor, eps, grid_mode, _p(n_arr),
+                             _p(lo_arr), _p(hi_arr), k, n_elem, n_s, _p(states), _p(rowptr),
+                             _p(cols), _p(solution), _p(c), _p(G), _p(gsol), _p(gst), _p(gb))
+    if rc != 0:
+        raise ValueError("oracle_backward rejected its arguments")
+    return gsol, gst, gb
+
+
+def workload_backward(wl, grad_limited, solution=None):
+    g = wl.grid
+    return backward(wl.dim, wl.gamma, wl.states, wl.rowptr, wl.cols, wl.n_s, g.mode,
+                    g.n[: wl.dim], g.lo, g.hi, g.k, wl.r_fac,
+                    wl.target if solution is None else solution, wl.node_weights, grad_limited)
 
 
 def delta(dim: int, gamma: float) -> float:

@@ -363,3 +363,335 @@ int oracle_limit(int d, double gamma, double p_floor, double eps,
     }
     return 0;
 }
+
+/* --------------------------------------------------------------- backward */
+
+/*
+ * Analytic subgradient of J through the limiter and the bounds, written out
+ * from the chain rule (a plain reference, not an efficient one).
+ *
+ * Forward chain per element e (Sec. 3.3-3.8): bounds b_e(states of S_e) and
+ * limited nodes w~_e(solution_e, b_e).  Given G = dJ/dw~ for every node, this
+ * returns dJ/dsolution (through the limiter) and dJ/dstates (through the
+ * bounds of every element whose stencil holds the state).
+ *
+ * Conventions: min/max ties pick the first candidate (stencil order for the
+ * envelopes, node order for extreme nodes, variable order for alpha_min);
+ * alpha capped at 1 or set to 0 by the epsilon rule is locally constant; a
+ * floored rho_min is constant; the indicator u_j < 0 of the momentum split
+ * contributes nothing because its integrand vanishes at u_j = 0.  In
+ * per-stencil (STENCIL) grid mode the box ends follow the extreme states of
+ * eq. truncdomain, so node positions and trapezoid weights carry gradient.
+ */
+
+/* Pressure gradient dP/dw for the ideal gas (Sec. 2.1). */
+static void pressure_grad(int d, double gamma, const double* w, double* g) {
+    double mm = 0.0;
+    for (int j = 0; j < d; ++j) mm += w[1 + j] * w[1 + j];
+    g[0] = (gamma - 1.0) * 0.5 * mm / (w[0] * w[0]);
+    for (int j = 0; j < d; ++j) g[1 + j] = -(gamma - 1.0) * w[1 + j] / w[0];
+    g[d + 1] = gamma - 1.0;
+}
+
+/*
+ * Limiter backward of one element.  w, out as in element_limit; G = dJ/dout;
+ * gw = dJ/dw (out), gb = dJ/db (out, 2nv).
+ */
+static void element_limit_backward(int d, double gamma, double p_floor, double eps, int n_s,
+                                   const double* w, const double* b, const double* c,
+                                   const double* G, double* gw, double* gb) {
+    const int nv = d + 2;
+    for (int i = 0; i < nv * n_s; ++i) gw[i] = 0.0;
+    for (int i = 0; i < 2 * nv; ++i) gb[i] = 0.0;
+    for (int v = 0; v < 2 * nv; ++v)
+        if (!isfinite(b[v])) {           /* passed through unchanged */
+            for (int i = 0; i < nv * n_s; ++i) gw[i] = G[i];
+            return;
+        }
+    double csum = 0.0;
+    for (int j = 0; j < n_s; ++j) csum += c[j];
+    double wbar[OR_MAXV];
+    for (int v = 0; v < nv; ++v) {
+        double acc = 0.0;
+        for (int j = 0; j < n_s; ++j) acc += c[j] * w[v * n_s + j];
+        wbar[v] = acc / csum;
+    }
+    /* recompute alpha and which term set it */
+    double amin = 1.0;
+    int vstar = -1, upper = 0, jstar = -1;
+    double dstar = 0.0;
+    for (int v = 0; v < nv; ++v) {
+        int jmax = 0, jmin = 0;
+        for (int j = 1; j < n_s; ++j) {
+            if (w[v * n_s + j] > w[v * n_s + jmax]) jmax = j;
+            if (w[v * n_s + j] < w[v * n_s + jmin]) jmin = j;
+        }
+        double dp = w[v * n_s + jmax] - wbar[v], dm = w[v * n_s + jmin] - wbar[v];
+        double av;
+        int vv = -1, up = 0, jj = -1;
+        double dd = 0.0;
+        if (fabs(dm) < eps || fabs(dp) < eps) av = 0.0;      /* constant */
+        else {
+            av = 1.0;
+            double ru = fabs((b[nv + v] - wbar[v]) / dp);
+            double rl = fabs((b[v] - wbar[v]) / dm);
+            if (ru < av) { av = ru; vv = v; up = 1; jj = jmax; dd = dp; }
+            if (rl < av) { av = rl; vv = v; up = 0; jj = jmin; dd = dm; }
+        }
+        if (av < amin) { amin = av; vstar = vv; upper = up; jstar = jj; dstar = dd; }
+    }
+    double wt[OR_MAXV * 64];
+    for (int v = 0; v < nv; ++v)
+        for (int j = 0; j < n_s; ++j) wt[v * n_s + j] = wbar[v] + amin * (w[v * n_s + j] - wbar[v]);
+    /* pressure step */
+    double pmin = INFINITY;
+    int jp = 0;
+    for (int j = 0; j < n_s; ++j) {
+        double wn[OR_MAXV];
+        for (int v = 0; v < nv; ++v) wn[v] = wt[v * n_s + j];
+        double P = pressure(d, gamma, wn);
+        if (isnan(P)) P = -INFINITY;
+        if (P < pmin) { pmin = P; jp = j; }
+    }
+    double gwt[OR_MAXV * 64];      /* dJ/dw~ */
+    double gwbar[OR_MAXV] = {0, 0, 0, 0};
+    if (pmin < p_floor) {
+        double pbar = pressure(d, gamma, wbar);
+        if (pbar > p_floor) {
+            double N = p_floor - pbar, D = pmin - pbar;
+            double aP = fabs(N / D);
+            double s = (N / D) >= 0 ? 1.0 : -1.0;
+            double gaP = 0.0;
+            for (int v = 0; v < nv; ++v)
+                for (int j = 0; j < n_s; ++j) {
+                    gwt[v * n_s + j] = aP * G[v * n_s + j];
+                    gaP += G[v * n_s + j] * (wt[v * n_s + j] - wbar[v]);
+                    gwbar[v] += (1.0 - aP) * G[v * n_s + j];
+                }
+            /* aP = s N / D: d aP = s (dN / D - N dD / D^2), dN = -dPbar, dD = dPmin - dPbar */
+            double gPbar = gaP * s * (-1.0 / D + N / (D * D));
+            double gPmin = gaP * s * (-N / (D * D));
+            double gp[OR_MAXV];
+            pressure_grad(d, gamma, wbar, gp);
+            for (int v = 0; v < nv; ++v) gwbar[v] += gPbar * gp[v];
+            double wn[OR_MAXV];
+            for (int v = 0; v < nv; ++v) wn[v] = wt[v * n_s + jp];
+            pressure_grad(d, gamma, wn, gp);
+            for (int v = 0; v < nv; ++v) gwt[v * n_s + jp] += gPmin * gp[v];
+        } else {
+            /* alpha_P = 0: every node equals the mean */
+            for (int v = 0; v < nv; ++v) {
+                for (int j = 0; j < n_s; ++j) { gwt[v * n_s + j] = 0.0; gwbar[v] += G[v * n_s + j]; }
+            }
+        }
+    } else {
+        for (int i = 0; i < nv * n_s; ++i) gwt[i] = G[i];
+    }
+    /* w~ = wbar + alpha (w - wbar) */
+    double galpha = 0.0;
+    for (int v = 0; v < nv; ++v)
+        for (int j = 0; j < n_s; ++j) {
+            gw[v * n_s + j] += amin * gwt[v * n_s + j];
+            gwbar[v] += (1.0 - amin) * gwt[v * n_s + j];
+            galpha += gwt[v * n_s + j] * (w[v * n_s + j] - wbar[v]);
+        }
+    if (vstar >= 0) {
+        /* alpha = |(bnd - wbar) / dd|, dd = w[jstar] - wbar */
+        const int v = vstar;
+        double bnd = upper ? b[nv + v] : b[v];
+        double r = (bnd - wbar[v]) / dstar;
+        double s = r >= 0 ? 1.0 : -1.0;
+        double g = galpha * s;
+        double gbnd = g / dstar;
+        double gdd = -g * (bnd - wbar[v]) / (dstar * dstar);
+        if (upper) gb[nv + v] += gbnd; else gb[v] += gbnd;
+        gwbar[v] += -gbnd;               /* from bnd - wbar */
+        gw[v * n_s + jstar] += gdd;      /* dd = w[jstar] - wbar */
+        gwbar[v] += -gdd;
+    }
+    /* wbar = sum c w / sum c */
+    for (int v = 0; v < nv; ++v)
+        for (int j = 0; j < n_s; ++j) gw[v * n_s + j] += gwbar[v] * c[j] / csum;
+}
+
+/*
+ * Bounds backward of one element: given gb = dJ/db (2nv), accumulate dJ/dstates
+ * into gstates (full [nv][n_nodes] array).
+ */
+static void element_bounds_backward(int d, double gamma, double r_fac, double rho_floor,
+                                    int grid_mode, const int* n, const double* lo_in,
+                                    const double* hi_in, double k, int n_s,
+                                    const double* states, int64_t n_elem,
+                                    const int* rowptr, const int* cols, int64_t e,
+                                    const double* gb_in, double* gstates) {
+    const int nv = d + 2;
+    const int64_t n_nodes = n_elem * n_s;
+    const int row0 = rowptr[e], row1 = rowptr[e + 1];
+    const int S = (row1 - row0) * n_s;
+    prim_t* st = (prim_t*)malloc(sizeof(prim_t) * (size_t)S);
+    int64_t* node = (int64_t*)malloc(sizeof(int64_t) * (size_t)S);
+    int s = 0;
+    for (int r = row0; r < row1; ++r)
+        for (int j = 0; j < n_s; ++j) {
+            node[s] = (int64_t)cols[r] * n_s + j;
+            st[s] = node_prim(d, gamma, states, n_nodes, node[s]);
+            ++s;
+        }
+    double gb[2 * OR_MAXV];
+    for (int i = 0; i < 2 * nv; ++i) gb[i] = gb_in[i];
+    /* recompute rho_min to know whether the floor was active */
+    double out[2 * OR_MAXV];
+    element_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo_in, hi_in, k, n_s, states,
+                   n_elem, rowptr[n_elem], rowptr, cols, e, out);
+    if (out[0] == rho_floor) gb[0] = 0.0;
+    const double delta = oracle_delta(d, gamma);
+
+    double lo[2] = {0, 0}, hi[2] = {0, 0}, h[2] = {0, 0};
+    int ilo[2] = {-1, -1}, ihi[2] = {-1, -1};
+    for (int j = 0; j < d; ++j) {
+        if (grid_mode == 0) { lo[j] = lo_in[j]; hi[j] = hi_in[j]; }
+        else {
+            lo[j] = INFINITY; hi[j] = -INFINITY;
+            for (int i = 0; i < S; ++i) {
+                double sd = sqrt(st[i].theta);
+                double a = st[i].U[j] - k * sd, bb = st[i].U[j] + k * sd;
+                if (a < lo[j]) { lo[j] = a; ilo[j] = i; }
+                if (bb > hi[j]) { hi[j] = bb; ihi[j] = i; }
+            }
+        }
+        h[j] = (hi[j] - lo[j]) / (double)(n[j] - 1);
+    }
+    /* per-state adjoints of (rho, U_1..U_d, theta) */
+    double* gp = (double*)calloc((size_t)S * (size_t)nv, sizeof(double));
+    double glo[2] = {0, 0}, ghi[2] = {0, 0};
+    const double rm = 1.0 - r_fac, rp = 1.0 + r_fac;
+    const int n1 = (d == 2) ? n[1] : 1;
+    for (int ty = 0; ty < n1; ++ty)
+        for (int tx = 0; tx < n[0]; ++tx) {
+            int t[2] = {tx, ty};
+            double u[2] = {0, 0}, M = 1.0;
+            for (int j = 0; j < d; ++j) {
+                u[j] = lo[j] + t[j] * h[j];
+                M *= h[j] * ((t[j] == 0 || t[j] == n[j] - 1) ? 0.5 : 1.0);
+            }
+            int win[4] = {0, 0, 0, 0};     /* Tmin, Tmax, Imin, Imax */
+            double fv[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
+            for (int i = 0; i < S; ++i) {
+                double g = maxwellian(d, &st[i], u);
+                double gI = 0.5 * st[i].theta * delta * g;
+                if (g < fv[0]) { fv[0] = g; win[0] = i; }
+                if (g > fv[1]) { fv[1] = g; win[1] = i; }
+                if (gI < fv[2]) { fv[2] = gI; win[2] = i; }
+                if (gI > fv[3]) { fv[3] = gI; win[3] = i; }
+            }
+            double hu2 = 0.0;
+            for (int j = 0; j < d; ++j) hu2 += 0.5 * u[j] * u[j];
+            /* adjoint weight Phi of each envelope (J = sum M Phi f) and dPhi/du_j */
+            double phi[4], dphi[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+            phi[0] = rm * (gb[0] + gb[d + 1] * hu2);
+            phi[1] = rp * (gb[nv] + gb[nv + d + 1] * hu2);
+            phi[2] = rm * gb[d + 1];
+            phi[3] = rp * gb[nv + d + 1];
+            for (int j = 0; j < d; ++j) {
+                /* m_min = sum_{u<0} u f_max + sum_{u>=0} u f_min ; m_max swapped */
+                double gmin = gb[1 + j], gmax = gb[nv + 1 + j];
+                if (u[j] < 0.0) { phi[1] += rp * gmin * u[j]; phi[0] += rm * gmax * u[j];
+                                  dphi[1][j] += rp * gmin; dphi[0][j] += rm * gmax; }
+                else            { phi[0] += rm * gmin * u[j]; phi[1] += rp * gmax * u[j];
+                                  dphi[0][j] += rm * gmin; dphi[1][j] += rp * gmax; }
+                dphi[0][j] += rm * gb[d + 1] * u[j];
+                dphi[1][j] += rp * gb[nv + d + 1] * u[j];
+            }
+            double Jt = 0.0, dJdu[2] = {0, 0};
+            for (int env = 0; env < 4; ++env) {
+                const prim_t* w = &st[win[env]];
+                double f = fv[env];
+                double wf = M * phi[env] * f;
+                Jt += wf;
+                double c2 = 0.0;
+                for (int j = 0; j < d; ++j) { double cc = u[j] - w->U[j]; c2 += cc * cc; }
+                /* d ln g / d(rho, U_j, theta) */
+                double* a = gp + (size_t)win[env] * nv;
+                a[0] += wf / w->rho;
+                for (int j = 0; j < d; ++j) a[1 + j] += wf * (u[j] - w->U[j]) / w->theta;
+                double dth = -0.5 * d / w->theta + 0.5 * c2 / (w->theta * w->theta);
+                if (env >= 2) dth += 1.0 / w->theta;   /* g_I carries theta delta / 2 */
+                a[d + 1] += wf * dth;
+                for (int j = 0; j < d; ++j)
+                    dJdu[j] += M * (dphi[env][j] * f - phi[env] * f * (u[j] - w->U[j]) / w->theta);
+            }
+            if (grid_mode == 1) {
+                for (int j = 0; j < d; ++j) {
+                    double fr = (double)t[j] / (double)(n[j] - 1);
+                    /* u = lo + t h, h = (hi - lo)/(n-1), M proportional to h_j */
+                    glo[j] += dJdu[j] * (1.0 - fr) - Jt / (h[j] * (n[j] - 1));
+                    ghi[j] += dJdu[j] * fr + Jt / (h[j] * (n[j] - 1));
+                }
+            }
+        }
+    if (grid_mode == 1)
+        for (int j = 0; j < d; ++j) {
+            /* lo = U - k sqrt(theta), hi = U + k sqrt(theta) of the extreme states */
+            double* a = gp + (size_t)ilo[j] * nv;
+            a[1 + j] += glo[j];
+            a[d + 1] += glo[j] * (-0.5 * k / sqrt(st[ilo[j]].theta));
+            a = gp + (size_t)ihi[j] * nv;
+            a[1 + j] += ghi[j];
+            a[d + 1] += ghi[j] * (0.5 * k / sqrt(st[ihi[j]].theta));
+        }
+    /* (rho, U, theta) -> (rho, m, E) */
+    for (int i = 0; i < S; ++i) {
+        const prim_t* w = &st[i];
+        const double* a = gp + (size_t)i * nv;
+        double U2 = 0.0;
+        for (int j = 0; j < d; ++j) U2 += w->U[j] * w->U[j];
+        double g_rho = a[0] + a[d + 1] * ((gamma - 1.0) * 0.5 * U2 - w->theta) / w->rho;
+        for (int j = 0; j < d; ++j) g_rho += a[1 + j] * (-w->U[j] / w->rho);
+        gstates[node[i]] += g_rho;
+        for (int j = 0; j < d; ++j)
+            gstates[(int64_t)(1 + j) * n_nodes + node[i]] +=
+                a[1 + j] / w->rho - a[d + 1] * (gamma - 1.0) * w->U[j] / w->rho;
+        gstates[(int64_t)(d + 1) * n_nodes + node[i]] += a[d + 1] * (gamma - 1.0) / w->rho;
+    }
+    free(gp); free(st); free(node);
+}
+
+/*
+ * Full backward: bounds from `states`, limiting of `solution`, G = dJ/dlimited.
+ * Outputs (all elements): gsol = dJ/dsolution [nv][n_nodes], gstates =
+ * dJ/dstates [nv][n_nodes], gbounds = dJ/dbounds [2nv][n_elem].
+ * Elements with non-finite bounds pass G through and contribute nothing to
+ * gstates.  Serial on purpose (gstates is accumulated across elements).
+ */
+int oracle_backward(int d, double gamma, double r_fac, double rho_floor, double p_floor,
+                    double eps, int grid_mode, const int* n, const double* lo, const double* hi,
+                    double k, int64_t n_elem, int n_s, const double* states, const int* rowptr,
+                    const int* cols, const double* solution, const double* c, const double* G,
+                    double* gsol, double* gstates, double* gbounds) {
+    if (d < 1 || d > 2 || n_s < 1 || n_s > 64) return -1;
+    const int nv = d + 2;
+    const int64_t n_nodes = n_elem * n_s;
+    for (int64_t i = 0; i < (int64_t)nv * n_nodes; ++i) gstates[i] = 0.0;
+    double* bnd = (double*)malloc(sizeof(double) * 2 * nv * (size_t)(n_elem > 0 ? n_elem : 1));
+    unsigned* st = (unsigned*)malloc(sizeof(unsigned) * (size_t)(n_elem > 0 ? n_elem : 1));
+    oracle_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k, n_elem, n_s,
+                  rowptr[n_elem], states, rowptr, cols, NULL, n_elem, bnd, st);
+    double w[OR_MAXV * 64], g[OR_MAXV * 64], gw[OR_MAXV * 64], b[2 * OR_MAXV], gb[2 * OR_MAXV];
+    for (int64_t e = 0; e < n_elem; ++e) {
+        for (int v = 0; v < nv; ++v)
+            for (int j = 0; j < n_s; ++j) {
+                w[v * n_s + j] = solution[(int64_t)v * n_nodes + e * n_s + j];
+                g[v * n_s + j] = G[(int64_t)v * n_nodes + e * n_s + j];
+            }
+        for (int v = 0; v < 2 * nv; ++v) b[v] = bnd[(int64_t)v * n_elem + e];
+        element_limit_backward(d, gamma, p_floor, eps, n_s, w, b, c, g, gw, gb);
+        for (int v = 0; v < nv; ++v)
+            for (int j = 0; j < n_s; ++j) gsol[(int64_t)v * n_nodes + e * n_s + j] = gw[v * n_s + j];
+        for (int v = 0; v < 2 * nv; ++v) gbounds[(int64_t)v * n_elem + e] = gb[v];
+        if (st[e] & (OR_ST_INADMISSIBLE | OR_ST_BAD_STENCIL)) continue;
+        element_bounds_backward(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k, n_s, states,
+                                n_elem, rowptr, cols, e, gb, gstates);
+    }
+    free(bnd); free(st);
+    return 0;
+}

@@ -287,7 +287,7 @@ def _vertex_stencil(tris: np.ndarray, n_vert: int):
 
 def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int = 64,
                       k: float = 4.0, gamma: float = 1.4, r_fac: float = 1e-3,
-                      jitter: float = 0.2, name: str = "tri") -> Workload:
+                      jitter: float = 0.2, outer=(1e-3, 1e-5), name: str = "tri") -> Workload:
     rng = _rng(seed)
     h = 1.0 / N
     iy, ix = np.divmod(np.arange((N + 1) * (N + 1)), N + 1)
@@ -314,8 +314,8 @@ def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int 
     Y = np.ascontiguousarray(Y.T)
     r = np.hypot(X - 0.5, Y - 0.5)
     inside = r < 0.3
-    rho = np.where(inside, 1.0, 1e-3) * (1.0 + 0.01 * _fourier(rng, X, Y))
-    pr = np.where(inside, 1.0, 1e-5) * (1.0 + 0.01 * _fourier(rng, X, Y))
+    rho = np.where(inside, 1.0, outer[0]) * (1.0 + 0.01 * _fourier(rng, X, Y))
+    pr = np.where(inside, 1.0, outer[1]) * (1.0 + 0.01 * _fourier(rng, X, Y))
     speed = 0.5 * np.where(inside, r / 0.3, 0.3 / np.maximum(r, 1e-12))
     rs = np.maximum(r, 1e-12)
     ux = speed * (X - 0.5) / rs + 0.005 * _fourier(rng, X, Y)

@@ -1,0 +1,104 @@
+"""Pins of the oracle's analytic subgradient against finite differences of the
+oracle's own forward pass (bounds + limiter), J = sum G * limited.
+
+Central differences with h = 1e-6 max(1, |x|); a DoF whose forward and
+backward one-sided differences disagree sits within h of a kink of the
+min/max envelopes or of the limiter's active set, and is only counted.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec
+
+
+def J_of(wl, states, solution, G):
+    g = wl.grid
+    b, _ = oracle.bounds(wl.dim, wl.gamma, states, wl.rowptr, wl.cols, wl.n_s, g.mode,
+                         g.n[: wl.dim], g.lo, g.hi, g.k, wl.r_fac)
+    lim, _, _ = oracle.limit(wl.dim, wl.gamma, solution, b, wl.node_weights, wl.n_s)
+    return float((G * lim).sum())
+
+
+def fd_check(wl, which, n_dofs=40, seed=0, tol=2e-5):
+    rng = np.random.default_rng(seed)
+    G = rng.standard_normal(wl.target.shape)
+    gsol, gst, _ = oracle.workload_backward(wl, G)
+    an = gst if which == "states" else gsol
+    base = {"states": wl.states, "solution": wl.target}
+    nv, nn = wl.states.shape
+    dofs = [(int(rng.integers(nv)), int(rng.integers(nn))) for _ in range(n_dofs)]
+    errs, kinks = [], 0
+    scale = np.abs(an).max()
+    J0 = abs(J_of(wl, wl.states, wl.target, G))
+    assert scale > 1e-6 * J0, "degenerate case: the gradient vanishes"
+    for v, i in dofs:
+        x = base[which]
+        h = 1e-6 * max(1.0, abs(x[v, i]))
+        vals = {}
+        for sgn in (-1, 0, 1):
+            y = x.copy()
+            y[v, i] += sgn * h
+            st = y if which == "states" else wl.states
+            so = y if which == "solution" else wl.target
+            vals[sgn] = J_of(wl, st, so, G)
+        fwd = (vals[1] - vals[0]) / h
+        bwd = (vals[0] - vals[-1]) / h
+        cen = (vals[1] - vals[-1]) / (2 * h)
+        if abs(fwd - bwd) > 1e-3 * (abs(cen) + 1e-3 * scale):
+            kinks += 1
+            continue
+        noise = 1e3 * np.finfo(float).eps * J0 / h      # rounding floor of the difference
+        errs.append(abs(cen - an[v, i]) / max(abs(an[v, i]), 1e-3 * scale, noise))
+    print(f"[fd] {wl.name} {which}: {len(errs)} smooth DoFs, max rel err "
+          f"{max(errs) if errs else 0:.2e}, {kinks} near kinks", flush=True)
+    assert len(errs) >= 0.7 * n_dofs
+    assert max(errs) < tol, max(errs)
+
+
+@pytest.mark.parametrize("which", ["states", "solution"])
+def test_line_global_grid(which):
+    wl = synth.make_line_workload(n_elem=6, seed=31, grid_nodes=64, name="fd_line")
+    fd_check(wl, which)
+
+
+@pytest.mark.parametrize("which", ["states", "solution"])
+def test_line_stencil_grid(which):
+    wl = synth.make_line_workload(n_elem=6, seed=32, name="fd_line_st")
+    wl.grid = GridSpec(GRID_STENCIL, (101, 1), k=5.0)
+    fd_check(wl, which)
+
+
+@pytest.mark.parametrize("which", ["states", "solution"])
+def test_quad_stencil_grid(which):
+    wl = synth.make_quad_workload(N=3, seed=33, grid_nodes=20, name="fd_quad")
+    fd_check(wl, which, n_dofs=30)
+
+
+def test_quad_global_grid_states():
+    wl = synth.make_quad_workload(N=3, seed=34, field_kind="sine", grid_nodes=24,
+                                  grid_mode=GRID_GLOBAL, name="fd_quad_gl")
+    wl.target = wl.states + 30.0 * (wl.target - wl.states)   # make the bounds bind
+    fd_check(wl, "states", n_dofs=30)
+
+
+def test_tri_stencil_grid_states():
+    wl = synth.make_tri_workload(N=2, seed=35, grid_nodes=16, outer=(0.5, 0.3), name="fd_tri")
+    wl.target = wl.states + 20.0 * (wl.target - wl.states)
+    fd_check(wl, "states", n_dofs=30)
+
+
+def test_pressure_step_gradient():
+    """Elements where the pressure step fires carry the alpha_P terms."""
+    wl = synth.make_line_workload(n_elem=6, seed=36, grid_nodes=64, r_fac=0.97, name="fd_pstep")
+    wl.target = wl.target.copy()
+    # wide (heavily relaxed) bounds keep alpha near 1; energy pushed below the
+    # kinetic energy at a few nodes makes their pressure negative
+    for i in (5, 13, 18):
+        wl.target[2, i] = 0.3 * 0.5 * wl.target[1, i] ** 2 / wl.target[0, i]
+    b, _ = oracle.workload_bounds(wl)
+    _, _, st = oracle.workload_limit(wl, b)
+    assert (st & oracle.ST_PSTEP).any()
+    fd_check(wl, "solution", n_dofs=40, seed=3)
