@@ -71,7 +71,8 @@ typedef enum {
 #define KBL_ST_MEAN_OUTSIDE  0x40u   /* element mean lies outside its bounds */
 #define KBL_ST_BAD_BOUNDS    0x80u   /* bounds not finite: element passed through unchanged */
 #define KBL_ST_BAD_STENCIL   0x100u  /* stencil row out of range (rowptr or cols): bounds are NaN */
-#define KBL_ST_TOO_LARGE     0x200u  /* mixed precision only: more than 256 stencil states, bounds are NaN */
+#define KBL_ST_TOO_LARGE     0x200u  /* mixed precision and backward: more than 256 stencil states (NaN bounds / zero gradient) */
+#define KBL_ST_ASYMMETRIC    0x400u  /* backward: a stencil neighbour does not list this element back */
 
 typedef struct {
     int32_t mode;       /* KBL_GRID_GLOBAL or KBL_GRID_STENCIL */
@@ -147,6 +148,49 @@ kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int3
                      const double* solution, const double* bounds,
                      const double* node_weights, double* limited, double* alpha,
                      uint32_t* elem_status, void* stream);
+
+/*
+ * kbl_backward_workspace_bytes - device workspace kbl_bounds_limit_backward
+ * needs: the recomputed forward bounds and status, dJ/dbounds, and one
+ * gradient slot per (stencil entry, node, variable): 8 (d+2) nnz n_s bytes
+ * plus O(n_elem).
+ */
+size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, int64_t nnz);
+
+/*
+ * kbl_bounds_limit_backward - gradient of J(limited) where
+ *   limited = kbl_limit(solution, kbl_compute_bounds(states)),
+ * given G = dJ/dlimited.  FP64 only.  The bounds are recomputed (nothing is
+ * kept from the forward call); the min/max envelopes take their subgradient
+ * at the first winning state in stencil order, the limiter at its active
+ * term (first node and variable on ties); alpha capped at 1, alpha set to 0
+ * by the epsilon rule, alpha_P = 0 and a floored rho_min are constants.  In
+ * KBL_GRID_STENCIL mode the velocity box moves with its extreme states and
+ * that dependence is differentiated too.
+ *
+ *   states, rowptr, cols, vgrid, solution, node_weights: as in the forward
+ *                calls.  The stencil relation must be symmetric (e lists J
+ *                iff J lists e), which face- and vertex-neighbour stencils
+ *                are; elements that violate it get KBL_ST_ASYMMETRIC.
+ *   grad_limited [d+2][n_elem*n_s] dJ/dlimited.
+ *   grad_states  out [d+2][n_elem*n_s] dJ/dstates (through the bounds).
+ *   grad_solution out [d+2][n_elem*n_s] dJ/dsolution (through the limiter).
+ *   grad_bounds  out [2(d+2)][n_elem] dJ/dbounds, or NULL.
+ *   elem_status  out [n_elem] forward bounds status plus KBL_ST_ASYMMETRIC /
+ *                KBL_ST_TOO_LARGE, or NULL.
+ *   workspace    device memory of at least kbl_backward_workspace_bytes().
+ * Stencils of more than 256 states contribute no state gradient
+ * (KBL_ST_TOO_LARGE).  Grids: up to 64 x 64 (d = 2), 2048 nodes (d = 1).
+ * The result is bitwise deterministic.
+ */
+kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
+                                     int32_t n_s, int64_t nnz, const double* states,
+                                     const int32_t* rowptr, const int32_t* cols,
+                                     const kbl_vgrid* vgrid, const double* solution,
+                                     const double* node_weights, const double* grad_limited,
+                                     double* grad_states, double* grad_solution,
+                                     double* grad_bounds, uint32_t* elem_status,
+                                     void* workspace, size_t workspace_bytes, void* stream);
 
 /* Human-readable text for a status code (static storage). */
 const char* kbl_status_string(kbl_status s);

@@ -36,6 +36,7 @@ ST_MEAN_OUTSIDE = 0x40
 ST_BAD_BOUNDS = 0x80
 ST_BAD_STENCIL = 0x100
 ST_TOO_LARGE = 0x200
+ST_ASYMMETRIC = 0x400
 
 
 class VGrid(C.Structure):
@@ -85,6 +86,13 @@ def _load():
         lib.kbl_limit.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
                                   P, P, P, P, P, P, P]
         lib.kbl_limit.restype = C.c_int
+        lib.kbl_backward_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int64]
+        lib.kbl_backward_workspace_bytes.restype = C.c_size_t
+        lib.kbl_bounds_limit_backward.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64,
+                                                  C.c_int32, C.c_int64, P, P, P,
+                                                  C.POINTER(VGrid), P, P, P, P, P, P, P, P,
+                                                  C.c_size_t, P]
+        lib.kbl_bounds_limit_backward.restype = C.c_int
         _lib = lib
     return _lib
 

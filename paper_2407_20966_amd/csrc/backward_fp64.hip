@@ -1,0 +1,404 @@
+// FP64 backward of the kinetic bounds (the differentiable form), gfx950.
+//
+// Given dJ/db per element (from the limiter backward), this computes dJ/d(state)
+// for every stencil state of every element, then gathers them per node.
+//
+// Per element (one workgroup, the FP64 forward's tiling):
+//  1. Prologue as in the forward (coefficients in LDS, velocity box); in
+//     per-stencil box mode the states that set each box end are located
+//     (first in stencil order on ties).
+//  2. The log-Maxwellian envelopes are recomputed together with their winning
+//     state per velocity node (strict comparisons: the first state wins ties).
+//     Nothing from the forward is stored.
+//  3. Per node and envelope, the adjoint weight Phi of the moment rows
+//     (eq. rhobounds, Ebounds, mmbounds, mpbounds with the relaxation of
+//     eq. relaxed, the internal part of Sec. 3.6 and the trapezoid weights of
+//     Sec. 3.7) times the envelope value gives that node's share of J; its
+//     derivative w.r.t. the winner's (rho, U, theta) is
+//       d ln g / d rho = 1/rho,  d/dU = (u - U)/theta,
+//       d/dtheta = -d/(2 theta) + |u - U|^2/(2 theta^2) (+ 1/theta for g_I).
+//     These are summed per winning state, in a fixed order (a loop over the
+//     states that won anywhere, each followed by a workgroup reduction), so
+//     the result is bitwise deterministic.
+//  4. In per-stencil box mode the node positions and trapezoid weights move
+//     with the box ends; their adjoint is accumulated per node and passed to
+//     the extreme states (lo = U - k sqrt(theta), hi = U + k sqrt(theta)).
+//  5. (rho, U, theta) adjoints are mapped to conserved variables and written
+//     to this element's stencil slots.
+// A gather kernel then sums, for each node, the slots that refer to it,
+// walking the (symmetric) stencil in CSR order.
+#include "bounds_common.h"
+
+namespace kbl {
+namespace {
+
+struct BwdArgs {
+    BoundsArgs f;              // forward geometry and parameters
+    const uint32_t* fstatus;   // forward status per element
+    const double* gbnd;        // [2nv][n_elem] dJ/dbounds
+    double* slot;              // [nv][nnz * n_s] per-slot state gradients (out)
+    uint32_t* status;          // backward status per element (or null)
+};
+
+template <int D, int NT>
+__device__ __forceinline__ void write_slots_zero(const BwdArgs& a, int64_t row0, int64_t S) {
+    const int64_t nslot = a.f.nnz * a.f.n_s;
+    for (int64_t s = threadIdx.x; s < S; s += NT)
+#pragma unroll
+        for (int v = 0; v < D + 2; ++v) a.slot[(int64_t)v * nslot + row0 * a.f.n_s + s] = 0.0;
+}
+
+template <int D, int BX, int BY, int TX, int TY>
+__global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
+    constexpr int NT = BX * BY;
+    constexpr int NV = D + 2;
+    constexpr int NW = NT / 64;
+    static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    __shared__ Coef sC[kMaxStates];
+    __shared__ double sZ[kMaxStates][5];
+    __shared__ uint32_t sMask[kMaxStates / 32];
+    __shared__ int sExt[4];
+    __shared__ Red red;
+
+    const BoundsArgs& p = a.f;
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
+    const int tx = tid % BX, ty = tid / BX;
+    const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    const int64_t nslot = p.nnz * p.n_s;
+
+    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+        const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
+        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {          // no addressable slots
+            if (a.status && tid == 0) a.status[e] = KBL_ST_BAD_STENCIL;
+            continue;
+        }
+        const int64_t S = (row1 - row0) * p.n_s;
+        const uint32_t fst = a.fstatus[e];
+        if (S > kMaxStates || (fst & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE))) {
+            write_slots_zero<D, NT>(a, row0, S);
+            if (a.status && tid == 0) a.status[e] = fst | (S > kMaxStates ? KBL_ST_TOO_LARGE : 0u);
+            continue;
+        }
+        double gb[2 * NV];
+#pragma unroll
+        for (int v = 0; v < 2 * NV; ++v) gb[v] = a.gbnd[(int64_t)v * p.n_elem + e];
+        if (fst & KBL_ST_RHO_FLOOR) gb[0] = 0.0;   // the floored rho_min is constant
+
+        double box[4];
+        __syncthreads();
+        stencil_prologue<D, NT>(p, row0, S, red, sC, box);
+        // states setting the box ends (first in stencil order)
+        if (tid < 4) sExt[tid] = 1 << 30;
+        for (int i = tid; i < kMaxStates / 32; i += NT) sMask[i] = 0u;
+        for (int s = tid; s < kMaxStates; s += NT)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sZ[s][k] = 0.0;
+        __syncthreads();
+        if (p.grid_mode == KBL_GRID_STENCIL) {
+            for (int s = tid; s < (int)S; s += NT) {
+                const Prim st = load_prim<D>(p, state_node(p, row0, s));
+                const double sd = sqrt(st.th);
+                if (st.ux - p.k * sd == box[0]) atomicMin(&sExt[0], s);
+                if (st.ux + p.k * sd == box[1]) atomicMin(&sExt[1], s);
+                if (D == 2) {
+                    if (st.uy - p.k * sd == box[2]) atomicMin(&sExt[2], s);
+                    if (st.uy + p.k * sd == box[3]) atomicMin(&sExt[3], s);
+                }
+            }
+        }
+        const double hx = (box[1] - box[0]) / (double)(p.nx - 1);
+        const double hy = D == 2 ? (box[3] - box[2]) / (double)(p.ny - 1) : 0.0;
+        double ux[TX], uy[TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+            const int x = tx + BX * i;
+            ux[i] = box[0] + (x < p.nx ? x : p.nx - 1) * hx;
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int y = ty + BY * j;
+            uy[j] = D == 2 ? box[2] + (y < p.ny ? y : p.ny - 1) * hy : 0.0;
+        }
+        // envelopes and their winners: Tmin, Tmax, Imin, Imax
+        double q[4][TX][TY];
+        int wn[4][TX][TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i)
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                q[0][i][j] = kInf; q[1][i][j] = -kInf; q[2][i][j] = kInf; q[3][i][j] = -kInf;
+                wn[0][i][j] = wn[1][i][j] = wn[2][i][j] = wn[3][i][j] = 0;
+            }
+        for (int s = 0; s < (int)S; ++s) {
+            const Coef c = sC[s];
+            double A[TX], AI[TX], B[TY];
+#pragma unroll
+            for (int i = 0; i < TX; ++i) {
+                const double d = ux[i] - c.ux;
+                const double t = c.nk * d;
+                A[i] = fma(t, d, c.a);
+                AI[i] = fma(t, d, c.al);
+            }
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const double d = uy[j] - c.uy;
+                B[j] = D == 2 ? (c.nk * d) * d : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const double qt = A[i] + B[j], qi = AI[i] + B[j];
+                    if (qt < q[0][i][j]) { q[0][i][j] = qt; wn[0][i][j] = s; }
+                    if (qt > q[1][i][j]) { q[1][i][j] = qt; wn[1][i][j] = s; }
+                    if (qi < q[2][i][j]) { q[2][i][j] = qi; wn[2][i][j] = s; }
+                    if (qi > q[3][i][j]) { q[3][i][j] = qi; wn[3][i][j] = s; }
+                }
+        }
+        // per node: adjoint weights, envelope shares (q is overwritten with
+        // M Phi f), box-end adjoints and the winner mask
+        double gl[2] = {0.0, 0.0}, gh[2] = {0.0, 0.0};
+        uint32_t mask[kMaxStates / 32];
+#pragma unroll
+        for (int k = 0; k < kMaxStates / 32; ++k) mask[k] = 0u;
+#pragma unroll
+        for (int i = 0; i < TX; ++i)
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const int x = tx + BX * i, y = ty + BY * j;
+                const bool valid = x < p.nx && (D == 1 || y < p.ny);
+                const double u[2] = {ux[i], uy[j]};
+                double M = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
+                if (D == 2) M *= hy * ((y == 0 || y == p.ny - 1) ? 0.5 : 1.0);
+                if (!valid) M = 0.0;
+                double hu2 = 0.5 * u[0] * u[0];
+                if (D == 2) hu2 += 0.5 * u[1] * u[1];
+                double phi[4], dphi[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+                phi[0] = rm * (gb[0] + gb[D + 1] * hu2);
+                phi[1] = rp * (gb[NV] + gb[NV + D + 1] * hu2);
+                phi[2] = rm * gb[D + 1];
+                phi[3] = rp * gb[NV + D + 1];
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    const double gmin = gb[1 + k], gmax = gb[NV + 1 + k];
+                    if (u[k] < 0.0) {
+                        phi[1] += rp * gmin * u[k]; phi[0] += rm * gmax * u[k];
+                        dphi[1][k] += rp * gmin; dphi[0][k] += rm * gmax;
+                    } else {
+                        phi[0] += rm * gmin * u[k]; phi[1] += rp * gmax * u[k];
+                        dphi[0][k] += rm * gmin; dphi[1][k] += rp * gmax;
+                    }
+                    dphi[0][k] += rm * gb[D + 1] * u[k];
+                    dphi[1][k] += rp * gb[NV + D + 1] * u[k];
+                }
+                double Jt = 0.0, dJdu[2] = {0.0, 0.0};
+#pragma unroll
+                for (int env = 0; env < 4; ++env) {
+                    const double f = exp(q[env][i][j]);
+                    const double wf = M * phi[env] * f;
+                    Jt += wf;
+                    const Coef& c = sC[wn[env][i][j]];
+                    const double cu[2] = {c.ux, c.uy};
+#pragma unroll
+                    for (int k = 0; k < D; ++k)
+                        dJdu[k] += M * dphi[env][k] * f + wf * 2.0 * c.nk * (u[k] - cu[k]);
+                    q[env][i][j] = wf;
+                    const int ws = wn[env][i][j];
+                    if (valid) {
+#pragma unroll
+                        for (int k = 0; k < kMaxStates / 32; ++k)
+                            if ((ws >> 5) == k) mask[k] |= 1u << (ws & 31);
+                    }
+                }
+                if (p.grid_mode == KBL_GRID_STENCIL && valid) {
+                    const int t[2] = {x, y};
+                    const int n[2] = {p.nx, p.ny};
+                    const double h[2] = {hx, hy};
+#pragma unroll
+                    for (int k = 0; k < D; ++k) {
+                        const double fr = (double)t[k] / (double)(n[k] - 1);
+                        gl[k] += dJdu[k] * (1.0 - fr) - Jt / (h[k] * (n[k] - 1));
+                        gh[k] += dJdu[k] * fr + Jt / (h[k] * (n[k] - 1));
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);
+            }
+#pragma unroll
+        for (int k = 0; k < kMaxStates / 32; ++k)
+            if (mask[k]) atomicOr(&sMask[k], mask[k]);
+        double ext[4] = {gl[0], gh[0], gl[1], gh[1]};
+        block_sum<NT, 4>(ext, red);      // valid in thread 0; contains the barriers
+        // per winning state, in a fixed order: sum the shares and their moments
+        for (int k = 0; k < kMaxStates / 32; ++k) {
+            uint32_t m = sMask[k];
+            while (m) {
+                const int s = 32 * k + __builtin_ctz(m);
+                m &= m - 1;
+                const Coef c = sC[s];
+                double z[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
+#pragma unroll
+                        for (int env = 0; env < 4; ++env) {
+                            const double wf = (wn[env][i][j] == s) ? q[env][i][j] : 0.0;
+                            z[0] += wf;
+                            z[1] += wf * dx;
+                            z[2] += wf * dy;
+                            z[3] += wf * (dx * dx + dy * dy);
+                            if (env >= 2) z[4] += wf;
+                        }
+                    }
+                block_sum<NT, 5>(z, red);
+                if (tid == 0)
+#pragma unroll
+                    for (int v = 0; v < 5; ++v) sZ[s][v] = z[v];
+            }
+        }
+        if (tid == 0)
+#pragma unroll
+            for (int k = 0; k < 4; ++k) red.v[0][8 + k] = ext[k];
+        __syncthreads();
+        const double gext[4] = {red.v[0][8], red.v[0][9], red.v[0][10], red.v[0][11]};
+        // (rho, U, theta) adjoints -> conserved variables, one thread per state
+        for (int s = tid; s < (int)S; s += NT) {
+            const int64_t node = state_node(p, row0, s);
+            const Prim st = load_prim<D>(p, node);
+            const double th = st.th;
+            double g_rho = sZ[s][0] / st.rho;
+            double gU[2] = {sZ[s][1] / th, sZ[s][2] / th};
+            double g_th = -0.5 * D / th * sZ[s][0] + 0.5 * sZ[s][3] / (th * th) + sZ[s][4] / th;
+            if (p.grid_mode == KBL_GRID_STENCIL) {
+                const double half_k_sd = 0.5 * p.k / sqrt(th);
+#pragma unroll
+                for (int k = 0; k < D; ++k) {
+                    if (s == sExt[2 * k]) { gU[k] += gext[2 * k]; g_th -= gext[2 * k] * half_k_sd; }
+                    if (s == sExt[2 * k + 1]) { gU[k] += gext[2 * k + 1]; g_th += gext[2 * k + 1] * half_k_sd; }
+                }
+            }
+            const double U[2] = {st.ux, st.uy};
+            double U2 = st.ux * st.ux;
+            if (D == 2) U2 += st.uy * st.uy;
+            double out_rho = g_rho + g_th * (p.gm1 * 0.5 * U2 - th) / st.rho;
+            const int64_t at = row0 * p.n_s + s;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                out_rho -= gU[k] * U[k] / st.rho;
+                a.slot[(int64_t)(1 + k) * nslot + at] = gU[k] / st.rho - g_th * p.gm1 * U[k] / st.rho;
+            }
+            a.slot[at] = out_rho;
+            a.slot[(int64_t)(D + 1) * nslot + at] = g_th * p.gm1 / st.rho;
+        }
+        if (a.status && tid == 0) a.status[e] = fst;
+        (void)lane; (void)wid; (void)NW;
+    }
+}
+
+// dJ/dstates[v][node] = sum over the elements e of the stencil row of the
+// node's element J (stencils are symmetric: J's row lists every element whose
+// stencil holds J) of the slot of J in row e.  Fixed CSR order: deterministic.
+template <int D>
+__global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* slot, double* gst) {
+    constexpr int NV = D + 2;
+    const int64_t nslot = p.nnz * p.n_s;
+    for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < p.n_nodes;
+         n += (int64_t)gridDim.x * 256) {
+        const int64_t J = n / p.n_s, jn = n % p.n_s;
+        double acc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+        const int64_t r0 = p.rowptr[J], r1 = p.rowptr[J + 1];
+        if (r0 >= 0 && r1 > r0 && r1 <= p.nnz) {
+            for (int64_t r = r0; r < r1; ++r) {
+                const int32_t e = p.cols[r];
+                if (e < 0 || e >= p.n_elem) continue;
+                const int64_t q0 = p.rowptr[e], q1 = p.rowptr[e + 1];
+                if (q0 < 0 || q1 <= q0 || q1 > p.nnz) continue;
+                for (int64_t k = q0; k < q1; ++k) {
+                    if (p.cols[k] == (int32_t)J) {
+#pragma unroll
+                        for (int v = 0; v < NV; ++v) acc[v] += slot[(int64_t)v * nslot + k * p.n_s + jn];
+                        break;
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gst[(int64_t)v * p.n_nodes + n] = acc[v];
+    }
+}
+
+// Flags elements whose stencil lists an element J whose own row does not list
+// them back (the gather would miss that slot).
+__global__ __launch_bounds__(256) void check_symmetric(BoundsArgs p, uint32_t* status) {
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < p.n_elem;
+         e += (int64_t)gridDim.x * 256) {
+        const int64_t r0 = p.rowptr[e], r1 = p.rowptr[e + 1];
+        if (r0 < 0 || r1 <= r0 || r1 > p.nnz) continue;
+        bool ok = true;
+        for (int64_t r = r0; r < r1 && ok; ++r) {
+            const int32_t J = p.cols[r];
+            if (J < 0 || J >= p.n_elem) continue;
+            const int64_t q0 = p.rowptr[J], q1 = p.rowptr[J + 1];
+            bool found = false;
+            if (q0 >= 0 && q1 > q0 && q1 <= p.nnz)
+                for (int64_t k = q0; k < q1; ++k)
+                    if (p.cols[k] == (int32_t)e) { found = true; break; }
+            ok = found;
+        }
+        if (!ok) status[e] |= KBL_ST_ASYMMETRIC;
+    }
+}
+
+template <int D, int BX, int BY, int TX, int TY>
+hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
+    const int64_t grid = a.f.n_elem < (int64_t)INT32_MAX ? a.f.n_elem : (int64_t)INT32_MAX;
+    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY>), dim3((unsigned)grid), dim3(BX * BY),
+                       0, stream, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
+                                  double* slot, double* grad_states, uint32_t* status, int dim,
+                                  hipStream_t stream) {
+    if (f.n_elem == 0) return hipSuccess;
+    BwdArgs a;
+    a.f = f;
+    a.fstatus = fstatus;
+    a.gbnd = gbnd;
+    a.slot = slot;
+    a.status = status;
+    hipError_t err;
+    if (dim == 2) {
+        const int n = f.nx > f.ny ? f.nx : f.ny;
+        if (n <= 16) err = launch_bwd<2, 16, 16, 1, 1>(a, stream);
+        else if (n <= 32) err = launch_bwd<2, 16, 16, 2, 2>(a, stream);
+        else if (n <= 48) err = launch_bwd<2, 16, 16, 3, 3>(a, stream);
+        else if (n <= 64) err = launch_bwd<2, 16, 16, 4, 4>(a, stream);
+        else return hipErrorInvalidValue;
+    } else {
+        if (f.nx <= 256) err = launch_bwd<1, 256, 1, 1, 1>(a, stream);
+        else if (f.nx <= 512) err = launch_bwd<1, 256, 1, 2, 1>(a, stream);
+        else if (f.nx <= 1024) err = launch_bwd<1, 256, 1, 4, 1>(a, stream);
+        else if (f.nx <= 2048) err = launch_bwd<1, 256, 1, 8, 1>(a, stream);
+        else return hipErrorInvalidValue;
+    }
+    if (err != hipSuccess) return err;
+    const int64_t blocks = (f.n_nodes + 255) / 256;
+    const unsigned g = (unsigned)(blocks < 65535 * 16 ? blocks : 65535 * 16);
+    if (dim == 2) hipLaunchKernelGGL(gather_slots<2>, dim3(g), dim3(256), 0, stream, f, slot, grad_states);
+    else hipLaunchKernelGGL(gather_slots<1>, dim3(g), dim3(256), 0, stream, f, slot, grad_states);
+    err = hipGetLastError();
+    if (err != hipSuccess || !status) return err;
+    const int64_t eb = (f.n_elem + 255) / 256;
+    hipLaunchKernelGGL(check_symmetric, dim3((unsigned)(eb < 65535 * 16 ? eb : 65535 * 16)),
+                       dim3(256), 0, stream, f, status);
+    return hipGetLastError();
+}
+
+}  // namespace kbl

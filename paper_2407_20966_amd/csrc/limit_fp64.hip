@@ -135,6 +135,197 @@ __global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
     }
 }
 
+template <int D>
+__device__ __forceinline__ void pressure_grad(double gm1, const double* w, double* g) {
+    const double mm = (D == 2) ? w[1] * w[1] + w[2] * w[2] : w[1] * w[1];
+    g[0] = gm1 * 0.5 * mm / (w[0] * w[0]);
+    g[1] = -gm1 * w[1] / w[0];
+    if (D == 2) g[2] = -gm1 * w[2] / w[0];
+    g[D + 1] = gm1;
+}
+
+// Value and first lane (within the group) of the group maximum / minimum.
+template <int G>
+__device__ __forceinline__ int grp_first(bool hit, int j) {
+    int idx = hit ? j : 1 << 30;
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) idx = min(idx, __shfl_xor(idx, o, 64));
+    return idx;
+}
+
+// Backward of the limiter: replays the forward decisions (same arithmetic as
+// limit_fp64) and applies the chain rule through the element mean, the
+// binding alpha term, the pressure step and the blends.  Ties pick the first
+// node / variable.  Writes dJ/dsolution per node and dJ/dbounds per element.
+template <int D, int G>
+__global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const double* grad,
+                                                           double* gsol, double* gbnd) {
+    constexpr int NV = D + 2;
+    constexpr int EPB = kThreads / G;
+    const int tid = threadIdx.x;
+    const int j = tid % G;
+    const int64_t e = (int64_t)blockIdx.x * EPB + tid / G;
+    const bool live = (e < p.n_elem) && (j < p.n_s);
+    const int64_t node = live ? e * p.n_s + j : 0;
+
+    double w[NV], Gw[NV];
+    const double c = live ? p.c[j] : 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        w[v] = live ? p.solution[(int64_t)v * p.n_nodes + node] : 0.0;
+        Gw[v] = live ? grad[(int64_t)v * p.n_nodes + node] : 0.0;
+    }
+    double b[2 * NV];
+    bool bad_b = false;
+#pragma unroll
+    for (int v = 0; v < 2 * NV; ++v) {
+        b[v] = (e < p.n_elem) ? p.bounds[(int64_t)v * p.n_elem + e] : 0.0;
+        bad_b |= !isfinite(b[v]);
+    }
+
+    double wbar[NV];
+    double amin = 1.0, dstar = 0.0;
+    int vstar = -1, upper = 0, jstar = -1;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        wbar[v] = grp_sum<G>(c * w[v]) * p.inv_csum;
+        const double wmax = grp_max<G>(live ? w[v] : -kInf);
+        const double wmin = grp_min<G>(live ? w[v] : kInf);
+        const int jmax = grp_first<G>(live && w[v] == wmax, j);
+        const int jmin = grp_first<G>(live && w[v] == wmin, j);
+        const double dp = wmax - wbar[v], dm = wmin - wbar[v];
+        double av;
+        int vv = -1, up = 0, jj = -1;
+        double dd = 0.0;
+        if (fabs(dm) < p.eps || fabs(dp) < p.eps) {
+            av = 0.0;
+        } else {
+            av = 1.0;
+            const double ru = fabs((b[NV + v] - wbar[v]) / dp);
+            const double rl = fabs((b[v] - wbar[v]) / dm);
+            if (ru < av) { av = ru; vv = v; up = 1; jj = jmax; dd = dp; }
+            if (rl < av) { av = rl; vv = v; up = 0; jj = jmin; dd = dm; }
+        }
+        if (av < amin) { amin = av; vstar = vv; upper = up; jstar = jj; dstar = dd; }
+    }
+    double wt[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + amin * (w[v] - wbar[v]);
+    double P = live ? pressure<D>(p.gm1, wt) : kInf;
+    if (isnan(P)) P = -kInf;
+    const double pmin = grp_min<G>(P);
+    const int jp = grp_first<G>(live && P == pmin, j);
+
+    double gwt[NV], gwbar[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gwbar[v] = 0.0;
+    if (pmin < p.p_floor) {
+        const double pbar = pressure<D>(p.gm1, wbar);
+        if (pbar > p.p_floor) {
+            const double N = p.p_floor - pbar, Dn = pmin - pbar;
+            const double aP = fabs(N / Dn);
+            const double sg = (N / Dn) >= 0.0 ? 1.0 : -1.0;
+            double gaP_l = 0.0;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                gwt[v] = aP * Gw[v];
+                gaP_l += Gw[v] * (wt[v] - wbar[v]);
+                gwbar[v] += grp_sum<G>((1.0 - aP) * Gw[v]);
+            }
+            const double gaP = grp_sum<G>(gaP_l);
+            const double gPbar = gaP * sg * (-1.0 / Dn + N / (Dn * Dn));
+            const double gPmin = gaP * sg * (-N / (Dn * Dn));
+            double gp[NV];
+            pressure_grad<D>(p.gm1, wbar, gp);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) gwbar[v] += gPbar * gp[v];
+            if (j == jp) {
+                pressure_grad<D>(p.gm1, wt, gp);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) gwt[v] += gPmin * gp[v];
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                gwt[v] = 0.0;
+                gwbar[v] += grp_sum<G>(Gw[v]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gwt[v] = Gw[v];
+    }
+    double gw[NV];
+    double ga_l = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        gw[v] = amin * gwt[v];
+        gwbar[v] += grp_sum<G>((1.0 - amin) * gwt[v]);
+        ga_l += gwt[v] * (w[v] - wbar[v]);
+    }
+    const double galpha = grp_sum<G>(ga_l);
+    double gb_term = 0.0;
+    if (vstar >= 0) {
+        double bnd = 0.0, wb = 0.0;          // register-array selects (no dynamic indexing)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v == vstar) { bnd = upper ? b[NV + v] : b[v]; wb = wbar[v]; }
+        const double r = (bnd - wb) / dstar;
+        const double g = galpha * (r >= 0.0 ? 1.0 : -1.0);
+        gb_term = g / dstar;
+        const double gdd = -g * (bnd - wb) / (dstar * dstar);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (v == vstar) gwbar[v] += -gb_term - gdd;
+        if (j == jstar) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+                if (v == vstar) gw[v] += gdd;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) gw[v] += gwbar[v] * c * p.inv_csum;
+
+    if (bad_b) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gw[v] = Gw[v];
+    }
+    if (live) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) gsol[(int64_t)v * p.n_nodes + node] = gw[v];
+        if (j == 0) {
+#pragma unroll
+            for (int v = 0; v < 2 * NV; ++v) {
+                const bool hit = !bad_b && vstar >= 0 && v == (upper ? NV + vstar : vstar);
+                gbnd[(int64_t)v * p.n_elem + e] = hit ? gb_term : 0.0;
+            }
+        }
+    }
+}
+
+template <int D, int G>
+hipError_t launch_bwd_g(const LimitArgs& a, const double* grad, double* gsol, double* gbnd,
+                        hipStream_t stream) {
+    constexpr int EPB = kThreads / G;
+    const int64_t blocks = (a.n_elem + EPB - 1) / EPB;
+    if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((limit_bwd_fp64<D, G>), dim3((unsigned)blocks), dim3(kThreads), 0, stream,
+                       a, grad, gsol, gbnd);
+    return hipGetLastError();
+}
+
+template <int D>
+hipError_t launch_bwd_d(const LimitArgs& a, const double* grad, double* gsol, double* gbnd,
+                        hipStream_t stream) {
+    if (a.n_s <= 1) return launch_bwd_g<D, 1>(a, grad, gsol, gbnd, stream);
+    if (a.n_s <= 2) return launch_bwd_g<D, 2>(a, grad, gsol, gbnd, stream);
+    if (a.n_s <= 4) return launch_bwd_g<D, 4>(a, grad, gsol, gbnd, stream);
+    if (a.n_s <= 8) return launch_bwd_g<D, 8>(a, grad, gsol, gbnd, stream);
+    if (a.n_s <= 16) return launch_bwd_g<D, 16>(a, grad, gsol, gbnd, stream);
+    if (a.n_s <= 32) return launch_bwd_g<D, 32>(a, grad, gsol, gbnd, stream);
+    return launch_bwd_g<D, 64>(a, grad, gsol, gbnd, stream);
+}
+
 template <int D, int G>
 hipError_t launch_g(const LimitArgs& a, hipStream_t stream) {
     constexpr int EPB = kThreads / G;
@@ -160,6 +351,13 @@ hipError_t launch_d(const LimitArgs& a, hipStream_t stream) {
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream) {
     if (a.n_elem == 0) return hipSuccess;
     return dim == 2 ? launch_d<2>(a, stream) : launch_d<1>(a, stream);
+}
+
+hipError_t launch_limit_bwd_fp64(const LimitArgs& a, int dim, const double* grad, double* gsol,
+                                 double* gbnd, hipStream_t stream) {
+    if (a.n_elem == 0) return hipSuccess;
+    return dim == 2 ? launch_bwd_d<2>(a, grad, gsol, gbnd, stream)
+                    : launch_bwd_d<1>(a, grad, gsol, gbnd, stream);
 }
 
 }  // namespace kbl

@@ -127,3 +127,68 @@ def limit(solution: torch.Tensor, bounds: torch.Tensor, node_weights, n_s: int,
     if rc != L.KBL_OK:
         raise L.KblError(rc, "kbl_limit")
     return out, alpha, status
+
+
+def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor,
+                          n_s: int, vgrid: L.VGrid, params: L.Params, solution: torch.Tensor,
+                          node_weights, grad_limited: torch.Tensor, stream=None):
+    """Gradients of J(limit(solution, bounds(states))) for G = dJ/dlimited.
+
+    Returns (dJ/dstates, dJ/dsolution, dJ/dbounds, status).  The workspace is
+    a torch allocation sized by kbl_backward_workspace_bytes.
+    """
+    _check(states, "states", torch.float64)
+    dev = states.device
+    for t, nm in ((solution, "solution"), (grad_limited, "grad_limited")):
+        _check(t, nm, torch.float64, dev)
+        if t.shape != states.shape:
+            raise ValueError(f"{nm} must have the shape of states")
+    _check(rowptr, "rowptr", torch.int32, dev)
+    _check(cols, "cols", torch.int32, dev)
+    dim = states.shape[0] - 2
+    n_elem = rowptr.numel() - 1
+    w = torch.as_tensor(node_weights, dtype=torch.float64).cpu().contiguous()
+    nbytes = L.lib().kbl_backward_workspace_bytes(dim, n_elem, int(n_s), cols.numel())
+    ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
+    gst = torch.empty_like(states)
+    gsol = torch.empty_like(states)
+    gb = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
+    status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    rc = L.lib().kbl_bounds_limit_backward(
+        C.byref(params), dim, n_elem, int(n_s), cols.numel(), _ptr(states), _ptr(rowptr),
+        _ptr(cols), C.byref(vgrid), _ptr(solution), C.c_void_p(w.data_ptr()),
+        _ptr(grad_limited), _ptr(gst), _ptr(gsol), _ptr(gb), _ptr(status), _ptr(ws),
+        ws.numel(), _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_bounds_limit_backward")
+    return gst, gsol, gb, status
+
+
+class KineticBoundsLimit(torch.autograd.Function):
+    """limited = limit(solution, bounds(states)) with the hand-written backward.
+
+    Gradients flow to `states` (through the kinetic bounds) and to `solution`
+    (through the limiter); nothing from the forward is kept besides the inputs.
+    """
+
+    @staticmethod
+    def forward(ctx, states, solution, rowptr, cols, n_s, vgrid, params, node_weights):
+        bounds, _ = compute_bounds(states, rowptr, cols, n_s, vgrid, params)
+        limited, _, _ = limit(solution, bounds, node_weights, n_s, params)
+        ctx.save_for_backward(states, solution, rowptr, cols)
+        ctx.n_s, ctx.vgrid, ctx.params, ctx.node_weights = n_s, vgrid, params, node_weights
+        return limited
+
+    @staticmethod
+    def backward(ctx, grad_limited):
+        states, solution, rowptr, cols = ctx.saved_tensors
+        gst, gsol, _, _ = bounds_limit_backward(states, rowptr, cols, ctx.n_s, ctx.vgrid,
+                                                ctx.params, solution, ctx.node_weights,
+                                                grad_limited.contiguous())
+        return gst, gsol, None, None, None, None, None, None
+
+
+def bounds_and_limit(states, solution, rowptr, cols, n_s, vgrid, params, node_weights):
+    """Differentiable bounds + limit (see KineticBoundsLimit)."""
+    return KineticBoundsLimit.apply(states, solution, rowptr, cols, n_s, vgrid, params,
+                                    node_weights)

@@ -29,7 +29,7 @@ def lib():
 def test_header_declares_expected_entry_points():
     syms = L.header_symbols()
     for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
-              "kbl_default_params"):
+              "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes"):
         assert s in syms
 
 
@@ -162,3 +162,29 @@ def test_limit_rejects_bad_params(lib):
     assert _limit(lib, _params(lib, 1.0), [1.0, 1.0]) == L.KBL_ERR_GAMMA
     assert _limit(lib, _params(lib), [1.0, 1.0], dim=4) == L.KBL_ERR_ARG
     assert _limit(lib, _params(lib), [1.0, 1.0], n_elem=-2) == L.KBL_ERR_ARG
+
+
+def _backward(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20, ws_bytes=None, weights=None):
+    w = np.ones(n_s) if weights is None else np.asarray(weights, dtype=np.float64)
+    need = lib.kbl_backward_workspace_bytes(dim, n_elem, n_s, nnz)
+    wsb = need if ws_bytes is None else ws_bytes
+    return lib.kbl_bounds_limit_backward(C.byref(p), dim, n_elem, n_s, nnz, FAKE, FAKE, FAKE,
+                                         C.byref(g), FAKE, w.ctypes.data_as(C.c_void_p), FAKE,
+                                         FAKE, FAKE, None, None, FAKE, wsb, None)
+
+
+def test_backward_workspace_size(lib):
+    # recomputed bounds + status + dJ/dbounds + one slot per (stencil entry, node, variable)
+    n = lib.kbl_backward_workspace_bytes(2, 1000, 16, 5000)
+    assert n >= 4 * 5000 * 16 * 8 + 2 * 8 * 1000 * 8 + 4 * 1000
+    assert lib.kbl_backward_workspace_bytes(3, 10, 4, 10) == 0
+
+
+def test_backward_rejects_bad_arguments(lib):
+    g = _grid()
+    assert _backward(lib, _params(lib), g, ws_bytes=16) == L.KBL_ERR_WORKSPACE
+    assert _backward(lib, _params(lib, precision=L.PREC_MIXED_FP16), g) == L.KBL_ERR_UNSUPPORTED
+    assert _backward(lib, _params(lib, gamma=1.0), g) == L.KBL_ERR_GAMMA
+    assert _backward(lib, _params(lib), _grid(n=(65, 48))) == L.KBL_ERR_GRID
+    assert _backward(lib, _params(lib), _grid(n=(2049, 2)), dim=1, n_s=4) == L.KBL_ERR_GRID
+    assert _backward(lib, _params(lib), g, weights=[1.0] * 15 + [0.0]) == L.KBL_ERR_ARG

@@ -1,0 +1,184 @@
+"""Hand-written backward (bounds + limiter) on the GPU.
+
+- against the oracle's analytic subgradient on small inputs (1e-10 of the
+  gradient scale), in 1D/2D, global and per-stencil velocity boxes, triangles;
+- against central finite differences of the GPU forward on the 512x512 quad
+  workload (200 seeded DoFs, h = 1e-7 max(1, |x|), J = sum w rho_limited with
+  w ~ N(0, 1); J is summed over the elements a DoF can affect only, so the
+  difference does not drown in the rounding of the full sum), tolerance 1e-6;
+- autograd wiring, determinism, and the symmetric-stencil check.
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kbl():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2407_20966_amd as kbl
+    return kbl
+
+
+def dev_inputs(kbl, wl):
+    dev = torch.device("cuda:0")
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    g = wl.grid
+    vg = kbl.make_vgrid(g.mode, g.n[: wl.dim], g.lo, g.hi, g.k)
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    return t(wl.states), t(wl.target), t(wl.rowptr), t(wl.cols), vg, prm
+
+
+def gpu_backward(kbl, wl, G):
+    st, tg, rp, cl, vg, prm = dev_inputs(kbl, wl)
+    gst, gsol, gb, s = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm, tg,
+                                                 wl.node_weights,
+                                                 torch.from_numpy(G).to(st.device))
+    torch.cuda.synchronize()
+    return gst.cpu().numpy(), gsol.cpu().numpy(), gb.cpu().numpy(), s.cpu().numpy().view(np.uint32)
+
+
+def compare_with_oracle(kbl, wl, seed=0, tol=1e-10):
+    G = np.random.default_rng(seed).standard_normal(wl.target.shape)
+    gst, gsol, gb, st = gpu_backward(kbl, wl, G)
+    rsol, rst, rgb = oracle.workload_backward(wl, G)
+    out = {}
+    for name, a, b in (("states", gst, rst), ("solution", gsol, rsol), ("bounds", gb, rgb)):
+        scale = max(np.abs(b).max(), 1e-300)
+        err = np.abs(a - b).max() / scale
+        out[name] = err
+        assert err <= tol, f"{wl.name} d/d{name}: {err:.3e}"
+    print(f"[bwd] {wl.name}: " + ", ".join(f"d/d{k} {v:.1e}" for k, v in out.items()), flush=True)
+    assert not (st & kbl.ST_ASYMMETRIC).any()
+    return out
+
+
+def test_line_global(kbl):
+    compare_with_oracle(kbl, synth.make_line_workload(n_elem=12, seed=41, name="b_line"))
+
+
+def test_line_stencil_box(kbl):
+    wl = synth.make_line_workload(n_elem=12, seed=42, name="b_line_st")
+    wl.grid = GridSpec(GRID_STENCIL, (300, 1), k=6.0)
+    compare_with_oracle(kbl, wl)
+
+
+@pytest.mark.parametrize("n", [16, 24, 37, 48, 64])
+def test_quad_stencil_box(kbl, n):
+    wl = synth.make_quad_workload(N=4, seed=43 + n, grid_nodes=n, name=f"b_quad{n}")
+    wl.target = wl.states + 10.0 * (wl.target - wl.states)
+    compare_with_oracle(kbl, wl)
+
+
+def test_quad_global_box(kbl):
+    wl = synth.make_quad_workload(N=4, seed=44, field_kind="sine", grid_nodes=32,
+                                  grid_mode=GRID_GLOBAL, name="b_quad_gl")
+    wl.target = wl.states + 30.0 * (wl.target - wl.states)
+    compare_with_oracle(kbl, wl)
+
+
+def test_tri_stencil_box(kbl):
+    wl = synth.make_tri_workload(N=3, seed=45, grid_nodes=24, outer=(0.5, 0.3), name="b_tri")
+    wl.target = wl.states + 20.0 * (wl.target - wl.states)
+    compare_with_oracle(kbl, wl)
+
+
+def test_pressure_step_and_shock(kbl):
+    wl = synth.make_tri_workload(N=3, seed=46, grid_nodes=24, name="b_tri_shock")
+    compare_with_oracle(kbl, wl)
+    wl2 = synth.make_line_workload(n_elem=8, seed=47, r_fac=0.97, name="b_pstep")
+    wl2.target = wl2.target.copy()
+    for i in (5, 13, 18):
+        wl2.target[2, i] = 0.3 * 0.5 * wl2.target[1, i] ** 2 / wl2.target[0, i]
+    compare_with_oracle(kbl, wl2)
+
+
+def test_quad512_finite_differences(kbl):
+    """Config of the differentiation form: full 512^2 mesh, 200 DoFs."""
+    wl = synth.make_workload("quad512")
+    rng = np.random.default_rng(240720966 + 4)
+    w = rng.standard_normal(wl.n_nodes)
+    G = np.zeros_like(wl.states)
+    G[0] = w
+    gst, gsol, _, _ = gpu_backward(kbl, wl, G)
+    grad = gst + gsol                  # the solution is W + Delta: both paths
+    st, tg, rp, cl, vg, prm = dev_inputs(kbl, wl)
+    wt = torch.from_numpy(w).to(st.device)
+
+    def J_local(elems):
+        b, _ = kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm)
+        lim, _, _ = kbl.limit(tg, b, wl.node_weights, wl.n_s, prm)
+        idx = torch.from_numpy((elems[:, None] * wl.n_s + np.arange(wl.n_s)).ravel()).to(st.device)
+        return float((lim[0, idx] * wt[idx]).sum().item())
+
+    n_dofs = 200
+    errs, kinks = [], 0
+    gscale = np.abs(grad).max()
+    for _ in range(n_dofs):
+        v = int(rng.integers(4))
+        n = int(rng.integers(wl.n_nodes))
+        E = n // wl.n_s
+        aff = np.unique(wl.cols[wl.rowptr[E]:wl.rowptr[E + 1]]).astype(np.int64)
+        x0 = float(wl.states[v, n])
+        h = 1e-7 * max(1.0, abs(x0))
+        vals = {}
+        for sgn in (-1, 0, 1):
+            st[v, n] = x0 + sgn * h
+            tg[v, n] = float(wl.target[v, n]) + sgn * h
+            vals[sgn] = J_local(aff)
+        st[v, n] = x0
+        tg[v, n] = float(wl.target[v, n])
+        fwd = (vals[1] - vals[0]) / h
+        bwd = (vals[0] - vals[-1]) / h
+        cen = (vals[1] - vals[-1]) / (2 * h)
+        if abs(fwd - bwd) > 1e-3 * (abs(cen) + 1e-6 * gscale):
+            kinks += 1
+            continue
+        noise = 1e3 * np.finfo(float).eps * max(abs(vals[0]), 1.0) / h
+        errs.append(abs(cen - grad[v, n]) / max(abs(grad[v, n]), 1e-6 * gscale, noise))
+    print(f"[fd-gpu] quad512: {len(errs)} smooth DoFs, max rel err {max(errs):.2e}, "
+          f"median {np.median(errs):.1e}, {kinks} within h of a kink", flush=True)
+    assert len(errs) >= 0.8 * n_dofs
+    assert max(errs) <= 1e-6
+
+
+def test_autograd_function(kbl):
+    wl = synth.make_quad_workload(N=6, seed=48, grid_nodes=32, name="b_autograd")
+    st, tg, rp, cl, vg, prm = dev_inputs(kbl, wl)
+    delta = (tg - st).detach()
+    x = st.clone().requires_grad_(True)
+    w = torch.from_numpy(np.random.default_rng(3).standard_normal(wl.n_nodes)).to(st.device)
+    lim = kbl.bounds_and_limit(x, x + delta, rp, cl, wl.n_s, vg, prm, wl.node_weights)
+    J = (lim[0] * w).sum()
+    J.backward()
+    G = torch.zeros_like(st)
+    G[0] = w
+    gst, gsol, _, _ = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm, tg, wl.node_weights, G)
+    torch.cuda.synchronize()
+    assert torch.equal(x.grad, gst + gsol)
+
+
+def test_backward_determinism(kbl):
+    wl = synth.make_quad_workload(N=8, seed=49, grid_nodes=48, name="b_det")
+    G = np.random.default_rng(1).standard_normal(wl.target.shape)
+    a = gpu_backward(kbl, wl, G)
+    b = gpu_backward(kbl, wl, G)
+    for x, y in zip(a, b):
+        assert np.array_equal(x.view(np.uint8), y.view(np.uint8))
+
+
+def test_asymmetric_stencil_flagged(kbl):
+    wl = synth.make_quad_workload(N=6, seed=50, grid_nodes=16, name="b_asym")
+    wl.cols = wl.cols.copy()
+    wl.cols[5 * 7 + 4] = 20           # element 7 lists element 20, which does not list 7
+    G = np.random.default_rng(2).standard_normal(wl.target.shape)
+    _, _, _, st = gpu_backward(kbl, wl, G)
+    assert st[7] & kbl.ST_ASYMMETRIC
