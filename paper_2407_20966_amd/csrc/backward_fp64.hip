@@ -99,11 +99,11 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
             for (int s = tid; s < (int)S; s += NT) {
                 const Prim st = load_prim<D>(p, state_node(p, row0, s));
                 const double sd = sqrt(st.th);
-                if (st.ux - p.k * sd == box[0]) atomicMin(&sExt[0], s);
-                if (st.ux + p.k * sd == box[1]) atomicMin(&sExt[1], s);
+                if (box_lo(st.ux, p.k, sd) == box[0]) atomicMin(&sExt[0], s);
+                if (box_hi(st.ux, p.k, sd) == box[1]) atomicMin(&sExt[1], s);
                 if (D == 2) {
-                    if (st.uy - p.k * sd == box[2]) atomicMin(&sExt[2], s);
-                    if (st.uy + p.k * sd == box[3]) atomicMin(&sExt[3], s);
+                    if (box_lo(st.uy, p.k, sd) == box[2]) atomicMin(&sExt[2], s);
+                    if (box_hi(st.uy, p.k, sd) == box[3]) atomicMin(&sExt[3], s);
                 }
             }
         }

@@ -71,6 +71,12 @@ struct Red {
     uint32_t flags;
 };
 
+// Ends of one state's velocity interval U -+ k sqrt(theta) (eq. truncdomain).
+// Written with an explicit fma so that every kernel rounds them identically
+// (the backward locates the extreme states by equality).
+__device__ __forceinline__ double box_lo(double u, double k, double sd) { return fma(-k, sd, u); }
+__device__ __forceinline__ double box_hi(double u, double k, double sd) { return fma(k, sd, u); }
+
 // Per-state coefficients of the log-Maxwellian (Sec. 2.2, Sec. 3.6).
 struct Coef {
     double a;    // ln rho - (d/2) ln(2 pi theta)
@@ -120,11 +126,11 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t 
         rl = fmax(rl, c.al);
         if (p.grid_mode == KBL_GRID_STENCIL) {
             const double sd = sqrt(st.th);
-            lx = fmin(lx, st.ux - p.k * sd);
-            hx = fmax(hx, st.ux + p.k * sd);
+            lx = fmin(lx, box_lo(st.ux, p.k, sd));
+            hx = fmax(hx, box_hi(st.ux, p.k, sd));
             if (D == 2) {
-                ly = fmin(ly, st.uy - p.k * sd);
-                hy = fmax(hy, st.uy + p.k * sd);
+                ly = fmin(ly, box_lo(st.uy, p.k, sd));
+                hy = fmax(hy, box_hi(st.uy, p.k, sd));
             }
         }
     }
