@@ -90,12 +90,15 @@ def main(argv=None):
     ap.add_argument("--workload", default="quad256")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default launch configuration instead of an autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs the bounds path on a single "
-              "MI355X (no multi-GPU path); use --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the bounds path runs on a single MI355X "
+              "(there is no multi-GPU path); use --gpus 1", file=sys.stderr)
         return 2
 
     import torch
@@ -140,6 +143,17 @@ def main(argv=None):
         print(f"[bench] copy calibration: {n * 8} bytes read, {n * 8} bytes written",
               file=sys.stderr, flush=True)
         del src, dst
+    tuned = {}
+
+    def autotune(name, p):
+        # untimed: picks the tile and launch shape for this problem shape
+        if args.no_autotune:
+            return
+        c = kbl.autotune_bounds(st, rp, cl, wl.n_s, vg, p, sample_elems=65536, stream=stream)
+        tuned[name] = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
+        print(f"[bench] autotuned {name}: {tuned[name]}", file=sys.stderr, flush=True)
+
+    autotune("fp64", prm)
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for _ in range(args.warmup):
         step()
@@ -195,6 +209,7 @@ def main(argv=None):
                 if ev is not None:
                     ev[2].record(stream)
 
+            autotune(name, prm_m)
             for _ in range(args.warmup):
                 mstep()
             torch.cuda.synchronize()
@@ -213,6 +228,51 @@ def main(argv=None):
             print(f"[bench] mixed {name}: {1e3 * mwall:.3f} ms/step (bounds {mb:.3f} ms)",
                   file=sys.stderr, flush=True)
         out["mixed"] = mixed
+    if tuned:
+        out["config"]["launch"] = {"autotuned": tuned,
+                                   "note": "workgroups_per_cu 0 = one workgroup per element"}
+    # the hand-written backward of bounds + limiter (FP64), J = sum w rho_limited
+    if not args.no_backward:
+        G = torch.zeros_like(tg)
+        G[0] = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n_nodes)).to(dev)
+        nbytes = kbl._lib.lib().kbl_backward_workspace_bytes(wl.dim, wl.n_elem, wl.n_s,
+                                                             int(cl.numel()))
+        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
+        gst = torch.empty_like(st)
+        gsol = torch.empty_like(st)
+        gbb = torch.empty_like(bounds)
+        bst = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+        wts = torch.as_tensor(wl.node_weights, dtype=torch.float64).contiguous()
+        import ctypes as C
+
+        def bstep():
+            rc = kbl._lib.lib().kbl_bounds_limit_backward(
+                C.byref(prm), wl.dim, wl.n_elem, wl.n_s, int(cl.numel()),
+                C.c_void_p(st.data_ptr()), C.c_void_p(rp.data_ptr()), C.c_void_p(cl.data_ptr()),
+                C.byref(vg), C.c_void_p(tg.data_ptr()), C.c_void_p(wts.data_ptr()),
+                C.c_void_p(G.data_ptr()), C.c_void_p(gst.data_ptr()), C.c_void_p(gsol.data_ptr()),
+                C.c_void_p(gbb.data_ptr()), C.c_void_p(bst.data_ptr()), C.c_void_p(ws.data_ptr()),
+                int(nbytes), C.c_void_p(stream.cuda_stream))
+            assert rc == 0, rc
+
+        for _ in range(max(1, args.warmup)):
+            bstep()
+        torch.cuda.synchronize()
+        bsteps = max(1, args.steps // 2)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(bsteps):
+            bstep()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        bms = e0.elapsed_time(e1) / bsteps
+        out["backward"] = {"value": wl.n_elem / (bms * 1e-3), "unit": "elements/s",
+                           "ms_per_call": bms, "vs_forward_step": bms / ms_step,
+                           "what": "kbl_bounds_limit_backward (recomputes FP64 bounds, limiter "
+                                   "backward, bounds backward, gather), J = sum w rho_limited"}
+        print(f"[bench] backward: {bms:.3f} ms/call", file=sys.stderr, flush=True)
+        del ws
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

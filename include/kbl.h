@@ -129,6 +129,29 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
                               uint32_t* elem_status, void* stream);
 
 /*
+ * kbl_autotune_bounds - picks the launch configuration of kbl_compute_bounds
+ * for this problem shape by timing every candidate on the caller's inputs:
+ * each tile configuration that fits the velocity grid, launched either with
+ * one workgroup per element or as a persistent grid of 1, 2, 4 or 8
+ * workgroups per compute unit (each workgroup then walks elements in a grid
+ * stride).  Timing uses the first `sample_elems` elements (all when <= 0).
+ * The choice is kept (per process) for later kbl_compute_bounds calls with
+ * the same dimension, precision, grid size, nodes per element and grid mode.
+ * Synchronises `stream`; leaves the full bounds of all elements in `bounds`
+ * (and the status in `elem_status` when non-null).  Returns 8 * tile + shape
+ * for the chosen candidate (tile: index of the tile configuration, 0 in 1D;
+ * shape: 0 = one workgroup per element, 1..4 = 1, 2, 4, 8 workgroups per
+ * compute unit), or -1 on bad arguments or a HIP failure.
+ */
+int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
+                            int64_t nnz, const double* states, const int32_t* rowptr,
+                            const int32_t* cols, const kbl_vgrid* vgrid, double* bounds,
+                            uint32_t* elem_status, int64_t sample_elems, void* stream);
+
+/* Forgets every choice made by kbl_autotune_bounds. */
+void kbl_autotune_clear(void);
+
+/*
  * kbl_limit - coupled squeeze limiter (Sec. 3.4, eq. alpha and eq. limiter,
  * with the epsilon rule) and pressure step (Sec. 3.8, eq. pmin and
  * eq. doublelimit), all in FP64.  Steps 5-7 of the overview in Sec. 3.9.

@@ -13,9 +13,9 @@ from ._lib import (  # noqa: F401
     LIB_PATH,
 )
 from .ops import (  # noqa: F401
-    KineticBoundsLimit, bounds_and_limit, bounds_limit_backward, compute_bounds, limit,
-    make_params, make_vgrid,
+    KineticBoundsLimit, autotune_bounds, bounds_and_limit, bounds_limit_backward,
+    compute_bounds, limit, make_params, make_vgrid,
 )
 
-__all__ = ["compute_bounds", "limit", "bounds_limit_backward", "bounds_and_limit",
+__all__ = ["compute_bounds", "limit", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
            "KineticBoundsLimit", "make_params", "make_vgrid", "KblError"]

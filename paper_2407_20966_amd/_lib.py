@@ -86,6 +86,12 @@ def _load():
         lib.kbl_limit.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
                                   P, P, P, P, P, P, P]
         lib.kbl_limit.restype = C.c_int
+        lib.kbl_autotune_bounds.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
+                                            C.c_int64, P, P, P, C.POINTER(VGrid), P, P,
+                                            C.c_int64, P]
+        lib.kbl_autotune_bounds.restype = C.c_int32
+        lib.kbl_autotune_clear.argtypes = []
+        lib.kbl_autotune_clear.restype = None
         lib.kbl_backward_workspace_bytes.argtypes = [C.c_int32, C.c_int64, C.c_int32, C.c_int64]
         lib.kbl_backward_workspace_bytes.restype = C.c_size_t
         lib.kbl_bounds_limit_backward.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64,

@@ -4,6 +4,11 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+#include <vector>
+
 #include "kbl_internal.h"
 
 namespace {
@@ -103,6 +108,38 @@ kbl_status make_limit_args(const kbl_params* params, int32_t dim, int64_t n_elem
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// ---------------------------------------------------------------- autotune
+// Launch choices found by kbl_autotune_bounds, per problem shape.
+struct TuneKey {
+    int dim, prec, nx, ny, n_s, mode;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(dim, prec, nx, ny, n_s, mode) < std::tie(o.dim, o.prec, o.nx, o.ny, o.n_s, o.mode);
+    }
+};
+struct TuneVal {
+    int tile;            // tile configuration index
+    int64_t blocks;      // 0 = one workgroup per element, else persistent grid size
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+TuneKey tune_key(const kbl::BoundsArgs& a, int dim, int prec) {
+    return TuneKey{dim, prec, a.nx, a.ny, a.n_s, a.grid_mode};
+}
+
+bool tuned(const TuneKey& k, TuneVal* v) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tune.find(k);
+    if (it == g_tune.end()) return false;
+    *v = it->second;
+    return true;
+}
+
+hipError_t launch_bounds_any(const kbl::BoundsArgs& a, int dim, int prec, int tile, hipStream_t st) {
+    return prec == KBL_PREC_FP64 ? kbl::launch_bounds_fp64(a, dim, st, tile)
+                                 : kbl::launch_bounds_mixed(a, prec, st, tile);
+}
+
 }  // namespace
 
 extern "C" {
@@ -150,17 +187,93 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
     if (prec != KBL_PREC_FP64 && dim != 2) return KBL_ERR_UNSUPPORTED;
     a.bounds = bounds;
     a.status = elem_status;
-    // KBL_BOUNDS_TILE / KBL_MIXED_TILE (tuning knobs) force a tile configuration
+    // launch choice: a tuning-knob override, else an autotuned choice, else the defaults
     int tile = -1;
-    if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE")) {
-        tile = atoi(env);
-        if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, a.nx, a.ny))
-            tile = -1;
+    TuneVal tv;
+    if (tuned(tune_key(a, dim, prec), &tv)) {
+        tile = tv.tile;
+        a.grid_blocks = tv.blocks;
     }
-    hipError_t err = prec == KBL_PREC_FP64
-                         ? kbl::launch_bounds_fp64(a, dim, (hipStream_t)stream, tile)
-                         : kbl::launch_bounds_mixed(a, prec, (hipStream_t)stream, tile);
+    if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE"))
+        tile = atoi(env);
+    if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
+    if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, a.nx, a.ny)) tile = -1;
+    hipError_t err = launch_bounds_any(a, dim, prec, tile, (hipStream_t)stream);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
+int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
+                            int64_t nnz, const double* states, const int32_t* rowptr,
+                            const int32_t* cols, const kbl_vgrid* vgrid, double* bounds,
+                            uint32_t* elem_status, int64_t sample_elems, void* stream) {
+    kbl::BoundsArgs a;
+    if (make_bounds_args(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid, kMax1DNodes,
+                         &a) != KBL_OK)
+        return -1;
+    const int prec = params->precision;
+    if (prec != KBL_PREC_FP64 && (dim != 2 || prec < KBL_PREC_MIXED_BF16 || prec > KBL_PREC_MIXED_FP32))
+        return -1;
+    if (n_elem == 0 || !bounds) return -1;
+    hipStream_t st = (hipStream_t)stream;
+    // candidates: every tile that fits the grid x {one workgroup per element,
+    // persistent grids of 1, 2, 4, 8 workgroups per CU}
+    std::vector<int> tiles;
+    if (dim == 2) {
+        const int nt = prec == KBL_PREC_FP64 ? kbl::bounds_tile_count_2d() : kbl::mixed_tile_count();
+        for (int t = 0; t < nt; ++t)
+            if (prec == KBL_PREC_FP64 ? kbl::bounds_tile_fits_2d(t, a.nx, a.ny)
+                                      : kbl::mixed_tile_fits_2d(t, a.nx, a.ny))
+                tiles.push_back(t);
+    } else {
+        tiles.push_back(-1);
+    }
+    int dev = 0, ncu = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    const int64_t shapes[] = {0, ncu, 2LL * ncu, 4LL * ncu, 8LL * ncu};
+    // time on a prefix of the elements (their rows are valid prefixes of the CSR)
+    kbl::BoundsArgs s = a;
+    s.n_elem = sample_elems > 0 && sample_elems < n_elem ? sample_elems : n_elem;
+    s.bounds = bounds;
+    s.status = elem_status;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return -1;
+    float best = 1e30f;
+    TuneVal bestv{-1, 0};
+    int best_idx = -1;
+    for (int t : tiles)
+        for (int si = 0; si < 5; ++si) {
+            const int64_t b = shapes[si];
+            s.grid_blocks = b;
+            bool ok = launch_bounds_any(s, dim, prec, t, st) == hipSuccess;   // warm-up
+            ok = ok && hipEventRecord(e0, st) == hipSuccess;
+            for (int r = 0; r < 2 && ok; ++r) ok = launch_bounds_any(s, dim, prec, t, st) == hipSuccess;
+            ok = ok && hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess;
+            float ms = 0.f;
+            if (ok && hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms < best) {
+                best = ms;
+                bestv = TuneVal{t, b};
+                best_idx = (t < 0 ? 0 : t) * 8 + si;
+            }
+        }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (best_idx < 0) return -1;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        g_tune[tune_key(a, dim, prec)] = bestv;
+    }
+    // leave the full result in `bounds`
+    a.bounds = bounds;
+    a.status = elem_status;
+    a.grid_blocks = bestv.blocks;
+    if (launch_bounds_any(a, dim, prec, bestv.tile, st) != hipSuccess) return -1;
+    return best_idx;
+}
+
+void kbl_autotune_clear(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
 }
 
 kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,

@@ -149,11 +149,16 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
             for (int i = 0; i < TX; ++i)
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
+                    // strict comparisons: the first state keeps a tie
                     const double qt = A[i] + B[j], qi = AI[i] + B[j];
-                    if (qt < q[0][i][j]) { q[0][i][j] = qt; wn[0][i][j] = s; }
-                    if (qt > q[1][i][j]) { q[1][i][j] = qt; wn[1][i][j] = s; }
-                    if (qi < q[2][i][j]) { q[2][i][j] = qi; wn[2][i][j] = s; }
-                    if (qi > q[3][i][j]) { q[3][i][j] = qi; wn[3][i][j] = s; }
+                    wn[0][i][j] = qt < q[0][i][j] ? s : wn[0][i][j];
+                    wn[1][i][j] = qt > q[1][i][j] ? s : wn[1][i][j];
+                    wn[2][i][j] = qi < q[2][i][j] ? s : wn[2][i][j];
+                    wn[3][i][j] = qi > q[3][i][j] ? s : wn[3][i][j];
+                    q[0][i][j] = fmin(q[0][i][j], qt);
+                    q[1][i][j] = fmax(q[1][i][j], qt);
+                    q[2][i][j] = fmin(q[2][i][j], qi);
+                    q[3][i][j] = fmax(q[3][i][j], qi);
                 }
         }
         // per node: adjoint weights, envelope shares (q is overwritten with
@@ -355,8 +360,7 @@ __global__ __launch_bounds__(256) void check_symmetric(BoundsArgs p, uint32_t* s
 
 template <int D, int BX, int BY, int TX, int TY>
 hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
-    const int64_t grid = a.f.n_elem < (int64_t)INT32_MAX ? a.f.n_elem : (int64_t)INT32_MAX;
-    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY>), dim3((unsigned)grid), dim3(BX * BY),
+    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY>), dim3(bounds_grid(a.f)), dim3(BX * BY),
                        0, stream, a);
     return hipGetLastError();
 }

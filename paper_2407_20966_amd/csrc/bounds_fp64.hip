@@ -245,8 +245,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
 
 template <typename K>
 hipError_t launch(K kernel, int threads, const BoundsArgs& a, hipStream_t stream) {
-    const int64_t grid = a.n_elem < (int64_t)INT32_MAX ? a.n_elem : (int64_t)INT32_MAX;
-    hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(threads), 0, stream, a);
+    hipLaunchKernelGGL(kernel, dim3(bounds_grid(a)), dim3(threads), 0, stream, a);
     return hipGetLastError();
 }
 

@@ -390,8 +390,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
 
 template <int TXW, int KS, int NW, int CT>
 hipError_t launch_mixed(const BoundsArgs& a, hipStream_t stream) {
-    const int64_t grid = a.n_elem < (int64_t)INT32_MAX ? a.n_elem : (int64_t)INT32_MAX;
-    hipLaunchKernelGGL((bounds_mixed_2d<TXW, KS, NW, CT>), dim3((unsigned)grid), dim3(NW * 64), 0,
+    hipLaunchKernelGGL((bounds_mixed_2d<TXW, KS, NW, CT>), dim3(bounds_grid(a)), dim3(NW * 64), 0,
                        stream, a);
     return hipGetLastError();
 }
@@ -435,6 +434,9 @@ int default_mixed_tile(int nx, int ny, int precision) {
 }
 
 }  // namespace
+
+int mixed_tile_count() { return kNumMixedTiles; }
+bool mixed_tile_fits_2d(int tile, int nx, int ny) { return mixed_tile_fits(tile, nx, ny); }
 
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile) {
     if (a.n_elem == 0) return hipSuccess;

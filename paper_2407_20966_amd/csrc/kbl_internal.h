@@ -29,7 +29,16 @@ struct BoundsArgs {
     double half_delta;  // delta / 2, delta = 2/(gamma-1) - d
     double r_fac;
     double rho_floor;
+    int64_t grid_blocks;  // host launch shape: 0 = one workgroup per element,
+                          // > 0 = persistent grid of that many workgroups
 };
+
+// Workgroups to launch for n_elem elements under a BoundsArgs::grid_blocks choice.
+inline unsigned bounds_grid(const BoundsArgs& a) {
+    int64_t g = a.grid_blocks > 0 && a.grid_blocks < a.n_elem ? a.grid_blocks : a.n_elem;
+    if (g > (int64_t)INT32_MAX) g = INT32_MAX;
+    return (unsigned)g;
+}
 
 // Arguments of the limiter kernel.
 constexpr int kMaxLimitNodes = 64;
@@ -55,6 +64,8 @@ struct LimitArgs {
 hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile);
 int bounds_tile_count_2d();
 bool bounds_tile_fits_2d(int tile, int nx, int ny);
+int mixed_tile_count();
+bool mixed_tile_fits_2d(int tile, int nx, int ny);
 // tile < 0 (or a tile that does not fit) selects the default for the grid size.
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);

@@ -98,6 +98,26 @@ def compute_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tenso
     return out, status
 
 
+def autotune_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor, n_s: int,
+                    vgrid: L.VGrid, params: L.Params, sample_elems: int = 32768,
+                    stream=None) -> int:
+    """Times the launch configurations of compute_bounds on these inputs and keeps
+    the fastest for this problem shape (see kbl_autotune_bounds).  Synchronises."""
+    _check(states, "states", torch.float64)
+    dev = states.device
+    dim = states.shape[0] - 2
+    n_elem = rowptr.numel() - 1
+    out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
+    status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    idx = L.lib().kbl_autotune_bounds(C.byref(params), dim, n_elem, int(n_s), cols.numel(),
+                                      _ptr(states), _ptr(rowptr), _ptr(cols), C.byref(vgrid),
+                                      _ptr(out), _ptr(status), int(sample_elems),
+                                      _stream(dev, stream))
+    if idx < 0:
+        raise L.KblError(L.KBL_ERR_ARG, "kbl_autotune_bounds")
+    return int(idx)
+
+
 def limit(solution: torch.Tensor, bounds: torch.Tensor, node_weights, n_s: int,
           params: L.Params, out: Optional[torch.Tensor] = None,
           alpha: Optional[torch.Tensor] = None, status: Optional[torch.Tensor] = None,

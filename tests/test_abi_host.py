@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_expected_entry_points():
     syms = L.header_symbols()
     for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
-              "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes"):
+              "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes",
+              "kbl_autotune_bounds", "kbl_autotune_clear"):
         assert s in syms
 
 
@@ -188,3 +189,18 @@ def test_backward_rejects_bad_arguments(lib):
     assert _backward(lib, _params(lib), _grid(n=(65, 48))) == L.KBL_ERR_GRID
     assert _backward(lib, _params(lib), _grid(n=(2049, 2)), dim=1, n_s=4) == L.KBL_ERR_GRID
     assert _backward(lib, _params(lib), g, weights=[1.0] * 15 + [0.0]) == L.KBL_ERR_ARG
+
+
+def _autotune(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20):
+    return lib.kbl_autotune_bounds(C.byref(p), dim, n_elem, n_s, nnz, FAKE, FAKE, FAKE,
+                                   C.byref(g), FAKE, None, 0, None)
+
+
+def test_autotune_rejects_bad_arguments(lib):
+    g = _grid()
+    assert _autotune(lib, _params(lib, gamma=1.0), g) == -1
+    assert _autotune(lib, _params(lib), _grid(n=(65, 48))) == -1
+    assert _autotune(lib, _params(lib, precision=7), g) == -1
+    assert _autotune(lib, _params(lib, precision=L.PREC_MIXED_FP16), _grid(n=(64, 2)), dim=1) == -1
+    assert _autotune(lib, _params(lib), g, n_elem=0) == -1
+    lib.kbl_autotune_clear()
