@@ -231,48 +231,56 @@ def main(argv=None):
     if tuned:
         out["config"]["launch"] = {"autotuned": tuned,
                                    "note": "workgroups_per_cu 0 = one workgroup per element"}
-    # the hand-written backward of bounds + limiter (FP64), J = sum w rho_limited
+    # the hand-written backward of bounds + limiter, J = sum w rho_limited; the
+    # forward's bounds and status are handed over (as the autograd Function does)
     if not args.no_backward:
         G = torch.zeros_like(tg)
         G[0] = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n_nodes)).to(dev)
-        nbytes = kbl._lib.lib().kbl_backward_workspace_bytes(wl.dim, wl.n_elem, wl.n_s,
-                                                             int(cl.numel()))
-        ws = torch.empty(int(nbytes), dtype=torch.uint8, device=dev)
-        gst = torch.empty_like(st)
-        gsol = torch.empty_like(st)
-        gbb = torch.empty_like(bounds)
-        bst = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
-        wts = torch.as_tensor(wl.node_weights, dtype=torch.float64).contiguous()
-        import ctypes as C
 
-        def bstep():
-            rc = kbl._lib.lib().kbl_bounds_limit_backward(
-                C.byref(prm), wl.dim, wl.n_elem, wl.n_s, int(cl.numel()),
-                C.c_void_p(st.data_ptr()), C.c_void_p(rp.data_ptr()), C.c_void_p(cl.data_ptr()),
-                C.byref(vg), C.c_void_p(tg.data_ptr()), C.c_void_p(wts.data_ptr()),
-                C.c_void_p(G.data_ptr()), C.c_void_p(gst.data_ptr()), C.c_void_p(gsol.data_ptr()),
-                C.c_void_p(gbb.data_ptr()), C.c_void_p(bst.data_ptr()), C.c_void_p(ws.data_ptr()),
-                int(nbytes), C.c_void_p(stream.cuda_stream))
-            assert rc == 0, rc
+        def time_backward(p):
+            fb = torch.empty_like(bounds)
+            fs = torch.empty_like(bstat)
+            kbl.compute_bounds(st, rp, cl, wl.n_s, vg, p, out=fb, status=fs, stream=stream)
 
-        for _ in range(max(1, args.warmup)):
-            bstep()
-        torch.cuda.synchronize()
-        bsteps = max(1, args.steps // 2)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(bsteps):
-            bstep()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        bms = e0.elapsed_time(e1) / bsteps
+            def bstep():
+                return kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, p, tg, wl.node_weights,
+                                                 G, fwd_bounds=fb, fwd_status=fs, stream=stream)
+
+            for _ in range(max(1, args.warmup)):
+                res = bstep()
+            torch.cuda.synchronize()
+            bsteps = max(1, args.steps // 2)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(bsteps):
+                bstep()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / bsteps, res[0] + res[1]
+
+        bms, gref = time_backward(prm)
         out["backward"] = {"value": wl.n_elem / (bms * 1e-3), "unit": "elements/s",
                            "ms_per_call": bms, "vs_forward_step": bms / ms_step,
-                           "what": "kbl_bounds_limit_backward (recomputes FP64 bounds, limiter "
-                                   "backward, bounds backward, gather), J = sum w rho_limited"}
+                           "what": "kbl_bounds_limit_backward given the forward bounds: limiter "
+                                   "backward, bounds backward (envelopes and winners recomputed), "
+                                   "gather; FP64; J = sum w rho_limited"}
         print(f"[bench] backward: {bms:.3f} ms/call", file=sys.stderr, flush=True)
-        del ws
+        if wl.dim == 2 and not args.no_mixed:
+            prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=kbl.PREC_MIXED_FP32)
+            mms, gmix = time_backward(prm_m)
+            scale = float(gref.abs().max())
+            diff = (gmix - gref).abs()
+            out["backward"]["mixed_fp32"] = {
+                "ms_per_call": mms, "speedup_vs_fp64": bms / mms,
+                "max_err_rel_to_max_grad": float(diff.max()) / scale,
+                "p99_err_rel_to_max_grad": float(torch.quantile(diff.flatten()[:1 << 24].float(),
+                                                                0.99)) / scale,
+                "what": "gradient of the mixed forward (FP32 envelopes and winners, FP64 "
+                        "shares and chain rule), compared with the FP64 gradient"}
+            print(f"[bench] mixed backward: {mms:.3f} ms/call, max err "
+                  f"{float(diff.max()) / scale:.2e} of the max gradient", file=sys.stderr,
+                  flush=True)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

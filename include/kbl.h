@@ -183,18 +183,32 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
 /*
  * kbl_bounds_limit_backward - gradient of J(limited) where
  *   limited = kbl_limit(solution, kbl_compute_bounds(states)),
- * given G = dJ/dlimited.  FP64 only.  The bounds are recomputed (nothing is
- * kept from the forward call); the min/max envelopes take their subgradient
- * at the first winning state in stencil order, the limiter at its active
- * term (first node and variable on ties); alpha capped at 1, alpha set to 0
- * by the epsilon rule, alpha_P = 0 and a floored rho_min are constants.  In
- * KBL_GRID_STENCIL mode the velocity box moves with its extreme states and
- * that dependence is differentiated too.
+ * given G = dJ/dlimited: the derivatives of eq. fminmax, relaxed, rhobounds,
+ * Ebounds, mmbounds, mpbounds, truncdomain (Sec. 3.3-3.7), the density floor
+ * and eq. alpha, limiter, pmin, doublelimit (Sec. 3.4, 3.8).  The min/max
+ * distributions are recomputed, never stored; the min/max envelopes take
+ * their subgradient at the first winning state in stencil order, the limiter
+ * at its active term (first node and variable on ties); alpha capped at 1,
+ * alpha set to 0 by the epsilon rule, alpha_P = 0 and a floored rho_min are
+ * constants.  In KBL_GRID_STENCIL mode the velocity box moves with its
+ * extreme states and that dependence is differentiated too.
+ *
+ * params->precision selects the forward being differentiated:
+ *   KBL_PREC_FP64   everything in FP64;
+ *   KBL_PREC_MIXED_* (d = 2) the mixed-precision forward: the limiter
+ *                backward runs on its bounds, and the envelope winners come
+ *                from FP32 envelopes of the same shifted, box-centred
+ *                coefficients; shares, moments and all chain-rule terms stay
+ *                FP64.
  *
  *   states, rowptr, cols, vgrid, solution, node_weights: as in the forward
  *                calls.  The stencil relation must be symmetric (e lists J
  *                iff J lists e), which face- and vertex-neighbour stencils
  *                are; elements that violate it get KBL_ST_ASYMMETRIC.
+ *   fwd_bounds   [2(d+2)][n_elem] the bounds kbl_compute_bounds returned for
+ *                these inputs and params, or NULL to recompute them in the
+ *                workspace.
+ *   fwd_status   the status that call returned (required with fwd_bounds).
  *   grad_limited [d+2][n_elem*n_s] dJ/dlimited.
  *   grad_states  out [d+2][n_elem*n_s] dJ/dstates (through the bounds).
  *   grad_solution out [d+2][n_elem*n_s] dJ/dsolution (through the limiter).
@@ -209,7 +223,8 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
 kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
                                      int32_t n_s, int64_t nnz, const double* states,
                                      const int32_t* rowptr, const int32_t* cols,
-                                     const kbl_vgrid* vgrid, const double* solution,
+                                     const kbl_vgrid* vgrid, const double* fwd_bounds,
+                                     const uint32_t* fwd_status, const double* solution,
                                      const double* node_weights, const double* grad_limited,
                                      double* grad_states, double* grad_solution,
                                      double* grad_bounds, uint32_t* elem_status,

@@ -97,7 +97,7 @@ def _load():
         lib.kbl_bounds_limit_backward.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64,
                                                   C.c_int32, C.c_int64, P, P, P,
                                                   C.POINTER(VGrid), P, P, P, P, P, P, P, P,
-                                                  C.c_size_t, P]
+                                                  P, P, C.c_size_t, P]
         lib.kbl_bounds_limit_backward.restype = C.c_int
         _lib = lib
     return _lib

@@ -46,6 +46,7 @@ def hipcc() -> str:
 SOURCE_FLAGS = {
     "bounds_fp64.hip": ["-fno-honor-nans"],
     "bounds_mixed.hip": ["-fno-honor-nans"],
+    "backward_fp64.hip": ["-fno-honor-nans"],
 }
 
 

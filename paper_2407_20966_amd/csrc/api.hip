@@ -228,8 +228,10 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
         tiles.push_back(-1);
     }
     int dev = 0, ncu = 256;
-    if (hipGetDevice(&dev) == hipSuccess)
-        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        ncu < 1)
+        ncu = 256;
     const int64_t shapes[] = {0, ncu, 2LL * ncu, 4LL * ncu, 8LL * ncu};
     // time on a prefix of the elements (their rows are valid prefixes of the CSR)
     kbl::BoundsArgs s = a;
@@ -256,8 +258,8 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
                 best_idx = (t < 0 ? 0 : t) * 8 + si;
             }
         }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     if (best_idx < 0) return -1;
     {
         std::lock_guard<std::mutex> lock(g_tune_mu);
@@ -303,7 +305,8 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
 kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
                                      int32_t n_s, int64_t nnz, const double* states,
                                      const int32_t* rowptr, const int32_t* cols,
-                                     const kbl_vgrid* vgrid, const double* solution,
+                                     const kbl_vgrid* vgrid, const double* fwd_bounds,
+                                     const uint32_t* fwd_status, const double* solution,
                                      const double* node_weights, const double* grad_limited,
                                      double* grad_states, double* grad_solution,
                                      double* grad_bounds, uint32_t* elem_status,
@@ -315,9 +318,14 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     kbl::LimitArgs la;
     rc = make_limit_args(params, dim, n_elem, n_s, node_weights, &la);
     if (rc != KBL_OK) return rc;
-    if (params->precision != KBL_PREC_FP64) return KBL_ERR_UNSUPPORTED;
+    const int prec = params->precision;
+    if (prec != KBL_PREC_FP64 && prec != KBL_PREC_MIXED_BF16 && prec != KBL_PREC_MIXED_FP16 &&
+        prec != KBL_PREC_MIXED_FP32)
+        return KBL_ERR_UNSUPPORTED;
+    if (prec != KBL_PREC_FP64 && dim != 2) return KBL_ERR_UNSUPPORTED;
     if (n_elem == 0) return KBL_OK;
     if (!solution || !grad_limited || !grad_states || !grad_solution) return KBL_ERR_ARG;
+    if (fwd_bounds && !fwd_status) return KBL_ERR_ARG;
     const size_t need = kbl_backward_workspace_bytes(dim, n_elem, n_s, nnz);
     if (!workspace || workspace_bytes < need) return KBL_ERR_WORKSPACE;
     const size_t nv = (size_t)dim + 2;
@@ -328,15 +336,28 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     double* wslot = (double*)ws;
     double* gbnd = grad_bounds ? grad_bounds : wgb;
     hipStream_t st = (hipStream_t)stream;
-    fa.bounds = wb;
-    fa.status = wst;
-    hipError_t err = kbl::launch_bounds_fp64(fa, dim, st, -1);
-    if (err != hipSuccess) return KBL_ERR_HIP;
+    hipError_t err;
+    const double* fb = fwd_bounds;
+    const uint32_t* fs = fwd_status;
+    if (!fb) {
+        // recompute the forward bounds (same precision, same launch choice)
+        fa.bounds = wb;
+        fa.status = wst;
+        int tile = -1;
+        TuneVal tv;
+        kbl::BoundsArgs ta = fa;
+        if (tuned(tune_key(fa, dim, prec), &tv)) { tile = tv.tile; ta.grid_blocks = tv.blocks; }
+        err = launch_bounds_any(ta, dim, prec, tile, st);
+        if (err != hipSuccess) return KBL_ERR_HIP;
+        fb = wb;
+        fs = wst;
+    }
     la.solution = solution;
-    la.bounds = wb;
+    la.bounds = fb;
     err = kbl::launch_limit_bwd_fp64(la, dim, grad_limited, grad_solution, gbnd, st);
     if (err != hipSuccess) return KBL_ERR_HIP;
-    err = kbl::launch_bounds_bwd_fp64(fa, wst, gbnd, wslot, grad_states, elem_status, dim, st);
+    err = kbl::launch_bounds_bwd_fp64(fa, fs, gbnd, wslot, grad_states, elem_status, dim,
+                                      prec != KBL_PREC_FP64, st);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 

@@ -17,8 +17,9 @@
 //     derivative w.r.t. the winner's (rho, U, theta) is
 //       d ln g / d rho = 1/rho,  d/dU = (u - U)/theta,
 //       d/dtheta = -d/(2 theta) + |u - U|^2/(2 theta^2) (+ 1/theta for g_I).
-//     These are summed per winning state, in a fixed order (a loop over the
-//     states that won anywhere, each followed by a workgroup reduction), so
+//     These are summed per winning state in a fixed order: each wave walks
+//     the winners among its own nodes in increasing state order (DPP wave
+//     sums, no barriers), and the per-wave sums are added in wave order, so
 //     the result is bitwise deterministic.
 //  4. In per-stencil box mode the node positions and trapezoid weights move
 //     with the box ends; their adjoint is accumulated per node and passed to
@@ -48,15 +49,22 @@ __device__ __forceinline__ void write_slots_zero(const BwdArgs& a, int64_t row0,
         for (int v = 0; v < D + 2; ++v) a.slot[(int64_t)v * nslot + row0 * a.f.n_s + s] = 0.0;
 }
 
-template <int D, int BX, int BY, int TX, int TY>
-__global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
+constexpr int kNoKey = 0x7fffffff;   // retired winner slot
+
+// Minimum waves per SIMD the register allocator targets.
+#ifndef KBL_BWD_WAVES
+#define KBL_BWD_WAVES 2
+#endif
+
+template <int D, int BX, int BY, int TX, int TY, bool F32>
+__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD_WAVES))) void bounds_bwd_fp64(BwdArgs a) {
     constexpr int NT = BX * BY;
-    constexpr int NV = D + 2;
     constexpr int NW = NT / 64;
     static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    static_assert(!F32 || D == 2, "the mixed-precision form is 2D");
     __shared__ Coef sC[kMaxStates];
-    __shared__ double sZ[kMaxStates][5];
-    __shared__ uint32_t sMask[kMaxStates / 32];
+    __shared__ CoefF sF[F32 ? kMaxStates : 1];
+    __shared__ double sZw[NW][kMaxStates][5];     // per-wave sums per winning state
     __shared__ int sExt[4];
     __shared__ Red red;
 
@@ -80,20 +88,37 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
             if (a.status && tid == 0) a.status[e] = fst | (S > kMaxStates ? KBL_ST_TOO_LARGE : 0u);
             continue;
         }
-        double gb[2 * NV];
+        double gb[2 * (D + 2)];
 #pragma unroll
-        for (int v = 0; v < 2 * NV; ++v) gb[v] = a.gbnd[(int64_t)v * p.n_elem + e];
+        for (int v = 0; v < 2 * (D + 2); ++v) gb[v] = a.gbnd[(int64_t)v * p.n_elem + e];
         if (fst & KBL_ST_RHO_FLOOR) gb[0] = 0.0;   // the floored rho_min is constant
+        constexpr int NV = D + 2;
 
-        double box[4];
+        double box[4], ref[2];
         __syncthreads();
-        stencil_prologue<D, NT>(p, row0, S, red, sC, box);
-        // states setting the box ends (first in stencil order)
+        stencil_prologue<D, NT>(p, row0, S, red, sC, box, F32 ? ref : nullptr);
+        const double cx = box[0] + 0.5 * (box[1] - box[0]);
+        const double cy = D == 2 ? box[2] + 0.5 * (box[3] - box[2]) : 0.0;
+        if (F32) {
+            // the mixed forward's FP32 coefficients (shifted, centred)
+            const bool has_i = p.half_delta > 0.0;
+            for (int s = tid; s < (int)S; s += NT) {
+                const Coef c = sC[s];
+                CoefF f;
+                f.a = (float)(c.a - ref[0]);
+                f.al = has_i ? (float)(c.al - ref[1]) : -kInfF;
+                f.ux = (float)(c.ux - cx);
+                f.uy = (float)(c.uy - cy);
+                f.nk = (float)c.nk;
+                sF[F32 ? s : 0] = f;
+            }
+        }
+        // states setting the box ends (first in stencil order); per-wave sums zeroed
         if (tid < 4) sExt[tid] = 1 << 30;
-        for (int i = tid; i < kMaxStates / 32; i += NT) sMask[i] = 0u;
-        for (int s = tid; s < kMaxStates; s += NT)
-#pragma unroll
-            for (int k = 0; k < 5; ++k) sZ[s][k] = 0.0;
+        for (int i = tid; i < NW * (int)S * 5; i += NT) {
+            const int w = i / (5 * (int)S), r = i - w * 5 * (int)S;
+            sZw[w][r / 5][r % 5] = 0.0;
+        }
         __syncthreads();
         if (p.grid_mode == KBL_GRID_STENCIL) {
             for (int s = tid; s < (int)S; s += NT) {
@@ -109,15 +134,17 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
         }
         const double hx = (box[1] - box[0]) / (double)(p.nx - 1);
         const double hy = D == 2 ? (box[3] - box[2]) / (double)(p.ny - 1) : 0.0;
+        // compact tiles: thread (tx, ty) owns nodes (TX tx + i, TY ty + j), so
+        // the winners a wave sees are few (winner regions are contiguous)
         double ux[TX], uy[TY];
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
-            const int x = tx + BX * i;
+            const int x = TX * tx + i;
             ux[i] = box[0] + (x < p.nx ? x : p.nx - 1) * hx;
         }
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
-            const int y = ty + BY * j;
+            const int y = TY * ty + j;
             uy[j] = D == 2 ? box[2] + (y < p.ny ? y : p.ny - 1) * hy : 0.0;
         }
         // envelopes and their winners: Tmin, Tmax, Imin, Imax
@@ -126,52 +153,100 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
 #pragma unroll
         for (int i = 0; i < TX; ++i)
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                q[0][i][j] = kInf; q[1][i][j] = -kInf; q[2][i][j] = kInf; q[3][i][j] = -kInf;
-                wn[0][i][j] = wn[1][i][j] = wn[2][i][j] = wn[3][i][j] = 0;
-            }
-        for (int s = 0; s < (int)S; ++s) {
-            const Coef c = sC[s];
-            double A[TX], AI[TX], B[TY];
-#pragma unroll
-            for (int i = 0; i < TX; ++i) {
-                const double d = ux[i] - c.ux;
-                const double t = c.nk * d;
-                A[i] = fma(t, d, c.a);
-                AI[i] = fma(t, d, c.al);
-            }
-#pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                const double d = uy[j] - c.uy;
-                B[j] = D == 2 ? (c.nk * d) * d : 0.0;
-            }
+            for (int j = 0; j < TY; ++j) wn[0][i][j] = wn[1][i][j] = wn[2][i][j] = wn[3][i][j] = 0;
+        if (!F32) {
 #pragma unroll
             for (int i = 0; i < TX; ++i)
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
-                    // strict comparisons: the first state keeps a tie
-                    const double qt = A[i] + B[j], qi = AI[i] + B[j];
-                    wn[0][i][j] = qt < q[0][i][j] ? s : wn[0][i][j];
-                    wn[1][i][j] = qt > q[1][i][j] ? s : wn[1][i][j];
-                    wn[2][i][j] = qi < q[2][i][j] ? s : wn[2][i][j];
-                    wn[3][i][j] = qi > q[3][i][j] ? s : wn[3][i][j];
-                    q[0][i][j] = fmin(q[0][i][j], qt);
-                    q[1][i][j] = fmax(q[1][i][j], qt);
-                    q[2][i][j] = fmin(q[2][i][j], qi);
-                    q[3][i][j] = fmax(q[3][i][j], qi);
+                    q[0][i][j] = kInf; q[1][i][j] = -kInf; q[2][i][j] = kInf; q[3][i][j] = -kInf;
                 }
+            for (int s = 0; s < (int)S; ++s) {
+                const Coef c = sC[s];
+                double A[TX], AI[TX], B[TY];
+#pragma unroll
+                for (int i = 0; i < TX; ++i) {
+                    const double d = ux[i] - c.ux;
+                    const double t = c.nk * d;
+                    A[i] = fma(t, d, c.a);
+                    AI[i] = fma(t, d, c.al);
+                }
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const double d = uy[j] - c.uy;
+                    B[j] = D == 2 ? (c.nk * d) * d : 0.0;
+                }
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        // strict comparisons: the first state keeps a tie
+                        const double qt = A[i] + B[j], qi = AI[i] + B[j];
+                        wn[0][i][j] = qt < q[0][i][j] ? s : wn[0][i][j];
+                        wn[1][i][j] = qt > q[1][i][j] ? s : wn[1][i][j];
+                        wn[2][i][j] = qi < q[2][i][j] ? s : wn[2][i][j];
+                        wn[3][i][j] = qi > q[3][i][j] ? s : wn[3][i][j];
+                        q[0][i][j] = fmin(q[0][i][j], qt);
+                        q[1][i][j] = fmax(q[1][i][j], qt);
+                        q[2][i][j] = fmin(q[2][i][j], qi);
+                        q[3][i][j] = fmax(q[3][i][j], qi);
+                    }
+            }
+        } else {
+            // winners from the FP32 envelopes; their FP64 log values are then
+            // recomputed from the FP64 coefficients of the winning states
+            float uxf[TX], uyf[TY], qf[4][TX][TY];
+#pragma unroll
+            for (int i = 0; i < TX; ++i) uxf[i] = (float)(ux[i] - cx);
+#pragma unroll
+            for (int j = 0; j < TY; ++j) uyf[j] = (float)(uy[j] - cy);
+#pragma unroll
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    qf[0][i][j] = kInfF; qf[1][i][j] = -kInfF; qf[2][i][j] = kInfF; qf[3][i][j] = -kInfF;
+                }
+            for (int s = 0; s < (int)S; ++s) {
+                const CoefF c = sF[F32 ? s : 0];
+                float A[TX], AI[TX], B[TY];
+#pragma unroll
+                for (int i = 0; i < TX; ++i) {
+                    const float d = uxf[i] - c.ux;
+                    const float t = c.nk * d;
+                    A[i] = fmaf(t, d, c.a);
+                    AI[i] = fmaf(t, d, c.al);
+                }
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const float d = uyf[j] - c.uy;
+                    B[j] = (c.nk * d) * d;
+                }
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        const float qt = A[i] + B[j], qi = AI[i] + B[j];
+                        wn[0][i][j] = qt < qf[0][i][j] ? s : wn[0][i][j];
+                        wn[1][i][j] = qt > qf[1][i][j] ? s : wn[1][i][j];
+                        wn[2][i][j] = qi < qf[2][i][j] ? s : wn[2][i][j];
+                        wn[3][i][j] = qi > qf[3][i][j] ? s : wn[3][i][j];
+                        qf[0][i][j] = fminf(qf[0][i][j], qt);
+                        qf[1][i][j] = fmaxf(qf[1][i][j], qt);
+                        qf[2][i][j] = fminf(qf[2][i][j], qi);
+                        qf[3][i][j] = fmaxf(qf[3][i][j], qi);
+                    }
+            }
+            // (the FP64 log values of the winners are recomputed per node below)
         }
         // per node: adjoint weights, envelope shares (q is overwritten with
-        // M Phi f), box-end adjoints and the winner mask
+        // M Phi f) and the box-end adjoints; nodes outside the grid retire
         double gl[2] = {0.0, 0.0}, gh[2] = {0.0, 0.0};
-        uint32_t mask[kMaxStates / 32];
-#pragma unroll
-        for (int k = 0; k < kMaxStates / 32; ++k) mask[k] = 0u;
+        int lk = kNoKey;                 // smallest winner still to be summed
 #pragma unroll
         for (int i = 0; i < TX; ++i)
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
-                const int x = tx + BX * i, y = ty + BY * j;
+                const int x = TX * tx + i, y = TY * ty + j;
                 const bool valid = x < p.nx && (D == 1 || y < p.ny);
                 const double u[2] = {ux[i], uy[j]};
                 double M = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
@@ -200,21 +275,22 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
                 double Jt = 0.0, dJdu[2] = {0.0, 0.0};
 #pragma unroll
                 for (int env = 0; env < 4; ++env) {
-                    const double f = exp(q[env][i][j]);
+                    const Coef& c = sC[wn[env][i][j]];
+                    double qv = F32 ? 0.0 : q[env][i][j];
+                    if (F32) {   // FP64 log value of the FP32 winner
+                        const double dx = u[0] - c.ux, dy = u[1] - c.uy;
+                        qv = fma(c.nk * dx, dx, env >= 2 ? c.al : c.a) + (c.nk * dy) * dy;
+                    }
+                    const double f = exp(qv);
                     const double wf = M * phi[env] * f;
                     Jt += wf;
-                    const Coef& c = sC[wn[env][i][j]];
                     const double cu[2] = {c.ux, c.uy};
 #pragma unroll
                     for (int k = 0; k < D; ++k)
                         dJdu[k] += M * dphi[env][k] * f + wf * 2.0 * c.nk * (u[k] - cu[k]);
                     q[env][i][j] = wf;
-                    const int ws = wn[env][i][j];
-                    if (valid) {
-#pragma unroll
-                        for (int k = 0; k < kMaxStates / 32; ++k)
-                            if ((ws >> 5) == k) mask[k] |= 1u << (ws & 31);
-                    }
+                    if (!valid) wn[env][i][j] = kNoKey;
+                    lk = min(lk, wn[env][i][j]);
                 }
                 if (p.grid_mode == KBL_GRID_STENCIL && valid) {
                     const int t[2] = {x, y};
@@ -229,53 +305,63 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
                 }
                 __builtin_amdgcn_sched_barrier(0);
             }
+        // per wave, winner by winner in increasing order: sum the shares and
+        // their moments about the winner's mean velocity (no barriers inside)
+        for (;;) {
+            const int s = wave_min_i32(lk);
+            if (s == kNoKey) break;
+            const Coef c = sC[s];
+            double z[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+            int nlk = kNoKey;
 #pragma unroll
-        for (int k = 0; k < kMaxStates / 32; ++k)
-            if (mask[k]) atomicOr(&sMask[k], mask[k]);
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
+                    const double d2 = dx * dx + dy * dy;
+#pragma unroll
+                    for (int env = 0; env < 4; ++env) {
+                        const bool m = wn[env][i][j] == s;
+                        const double wf = m ? q[env][i][j] : 0.0;
+                        z[0] += wf;
+                        z[1] = fma(wf, dx, z[1]);
+                        if (D == 2) z[2] = fma(wf, dy, z[2]);
+                        z[3] = fma(wf, d2, z[3]);
+                        if (env >= 2) z[4] += wf;
+                        wn[env][i][j] = m ? kNoKey : wn[env][i][j];
+                        nlk = min(nlk, wn[env][i][j]);
+                    }
+                }
+            lk = nlk;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) z[k] = wave_sum(z[k]);
+            if (lane == 0)
+#pragma unroll
+                for (int k = 0; k < 5; ++k) sZw[wid][s][k] = z[k];
+        }
         double ext[4] = {gl[0], gh[0], gl[1], gh[1]};
         block_sum<NT, 4>(ext, red);      // valid in thread 0; contains the barriers
-        // per winning state, in a fixed order: sum the shares and their moments
-        for (int k = 0; k < kMaxStates / 32; ++k) {
-            uint32_t m = sMask[k];
-            while (m) {
-                const int s = 32 * k + __builtin_ctz(m);
-                m &= m - 1;
-                const Coef c = sC[s];
-                double z[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
-#pragma unroll
-                    for (int j = 0; j < TY; ++j) {
-                        const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
-#pragma unroll
-                        for (int env = 0; env < 4; ++env) {
-                            const double wf = (wn[env][i][j] == s) ? q[env][i][j] : 0.0;
-                            z[0] += wf;
-                            z[1] += wf * dx;
-                            z[2] += wf * dy;
-                            z[3] += wf * (dx * dx + dy * dy);
-                            if (env >= 2) z[4] += wf;
-                        }
-                    }
-                block_sum<NT, 5>(z, red);
-                if (tid == 0)
-#pragma unroll
-                    for (int v = 0; v < 5; ++v) sZ[s][v] = z[v];
-            }
-        }
         if (tid == 0)
 #pragma unroll
             for (int k = 0; k < 4; ++k) red.v[0][8 + k] = ext[k];
         __syncthreads();
         const double gext[4] = {red.v[0][8], red.v[0][9], red.v[0][10], red.v[0][11]};
-        // (rho, U, theta) adjoints -> conserved variables, one thread per state
+        // (rho, U, theta) adjoints -> conserved variables, one thread per state;
+        // the per-wave sums are combined in wave order
         for (int s = tid; s < (int)S; s += NT) {
+            double z[5];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                z[k] = sZw[0][s][k];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) z[k] += sZw[w][s][k];
+            }
             const int64_t node = state_node(p, row0, s);
             const Prim st = load_prim<D>(p, node);
             const double th = st.th;
-            double g_rho = sZ[s][0] / st.rho;
-            double gU[2] = {sZ[s][1] / th, sZ[s][2] / th};
-            double g_th = -0.5 * D / th * sZ[s][0] + 0.5 * sZ[s][3] / (th * th) + sZ[s][4] / th;
+            double g_rho = z[0] / st.rho;
+            double gU[2] = {z[1] / th, z[2] / th};
+            double g_th = -0.5 * D / th * z[0] + 0.5 * z[3] / (th * th) + z[4] / th;
             if (p.grid_mode == KBL_GRID_STENCIL) {
                 const double half_k_sd = 0.5 * p.k / sqrt(th);
 #pragma unroll
@@ -298,7 +384,6 @@ __global__ __launch_bounds__(BX * BY) void bounds_bwd_fp64(BwdArgs a) {
             a.slot[(int64_t)(D + 1) * nslot + at] = g_th * p.gm1 / st.rho;
         }
         if (a.status && tid == 0) a.status[e] = fst;
-        (void)lane; (void)wid; (void)NW;
     }
 }
 
@@ -358,10 +443,10 @@ __global__ __launch_bounds__(256) void check_symmetric(BoundsArgs p, uint32_t* s
     }
 }
 
-template <int D, int BX, int BY, int TX, int TY>
+template <int D, int BX, int BY, int TX, int TY, bool F32 = false>
 hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY>), dim3(bounds_grid(a.f)), dim3(BX * BY),
-                       0, stream, a);
+    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY, F32>), dim3(bounds_grid(a.f)),
+                       dim3(BX * BY), 0, stream, a);
     return hipGetLastError();
 }
 
@@ -369,7 +454,7 @@ hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
 
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
                                   double* slot, double* grad_states, uint32_t* status, int dim,
-                                  hipStream_t stream) {
+                                  bool mixed, hipStream_t stream) {
     if (f.n_elem == 0) return hipSuccess;
     BwdArgs a;
     a.f = f;
@@ -378,7 +463,16 @@ hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, 
     a.slot = slot;
     a.status = status;
     hipError_t err;
-    if (dim == 2) {
+    if (dim == 2 && mixed) {
+        const int n = f.nx > f.ny ? f.nx : f.ny;
+        if (n <= 16) err = launch_bwd<2, 16, 16, 1, 1, true>(a, stream);
+        else if (n <= 32) err = launch_bwd<2, 16, 16, 2, 2, true>(a, stream);
+        else if (n <= 48) err = launch_bwd<2, 16, 16, 3, 3, true>(a, stream);
+        else if (n <= 64) err = launch_bwd<2, 16, 16, 4, 4, true>(a, stream);
+        else return hipErrorInvalidValue;
+    } else if (mixed) {
+        return hipErrorInvalidValue;
+    } else if (dim == 2) {
         const int n = f.nx > f.ny ? f.nx : f.ny;
         if (n <= 16) err = launch_bwd<2, 16, 16, 1, 1>(a, stream);
         else if (n <= 32) err = launch_bwd<2, 16, 16, 2, 2>(a, stream);

@@ -49,20 +49,55 @@ __device__ __forceinline__ Prim load_prim(const BoundsArgs& p, int64_t node) {
     return s;
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+// Wave64 reductions on the DPP lane network (no LDS round trips).  Inside
+// each row of 16 lanes: swap neighbours, swap pairs (quad_perm), then the
+// half-row and row mirrors; every lane of a row then holds the row result,
+// bit-identical across the row because each step combines the same two
+// operands.  The four row results are read out with readlane and combined
+// in a fixed order, so the wave result is deterministic and uniform.  All 64
+// lanes must be active.
+constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
+constexpr int kDppHalfMirror = 0x141;   // row_half_mirror
+constexpr int kDppMirror = 0x140;       // row_mirror
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double wave_min(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+__device__ __forceinline__ double lane_f64(double v, int lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+
+struct OpSum { __device__ static double f(double a, double b) { return a + b; } };
+struct OpMin { __device__ static double f(double a, double b) { return fmin(a, b); } };
+struct OpMax { __device__ static double f(double a, double b) { return fmax(a, b); } };
+
+template <class Op>
+__device__ __forceinline__ double wave_reduce(double v) {
+    v = Op::f(v, dpp_f64<kDppXor1>(v));
+    v = Op::f(v, dpp_f64<kDppXor2>(v));
+    v = Op::f(v, dpp_f64<kDppHalfMirror>(v));
+    v = Op::f(v, dpp_f64<kDppMirror>(v));
+    return Op::f(Op::f(lane_f64(v, 0), lane_f64(v, 16)), Op::f(lane_f64(v, 32), lane_f64(v, 48)));
+}
+__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
+__device__ __forceinline__ double wave_min(double v) { return wave_reduce<OpMin>(v); }
+__device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppHalfMirror, 0xF, 0xF, false));
+    v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppMirror, 0xF, 0xF, false));
+    return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+               min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
 // Shared scratch for the per-element prologue and epilogue (up to 4 waves).
@@ -83,6 +118,16 @@ struct Coef {
     double al;   // a + ln(theta delta / 2)   (-inf when delta == 0)
     double ux, uy;
     double nk;   // -1 / (2 theta)
+};
+
+// FP32 coefficients of the mixed-precision forms: shifted by the element's
+// log-peak references and centred on the velocity box.
+struct CoefF {
+    float a;    // a - ref_T
+    float al;   // a + l - ref_I   (-inf without internal degrees of freedom)
+    float ux;   // U_x - box centre
+    float uy;   // U_y - box centre
+    float nk;   // -1 / (2 theta)
 };
 
 template <int D>
@@ -197,7 +242,9 @@ __device__ __forceinline__ void store_bounds(const BoundsArgs& p, int64_t e, con
 
 template <int D>
 __device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32_t flags) {
-    const double nan = __builtin_nan("");
+    // quiet NaN by its bit pattern (these translation units assume no NaN
+    // arithmetic, but a stored pattern is just data)
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
     for (int v = 0; v < 2 * (D + 2); ++v) p.bounds[(int64_t)v * p.n_elem + e] = nan;
     if (p.status) p.status[e] = flags;
 }

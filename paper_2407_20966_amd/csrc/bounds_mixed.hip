@@ -46,14 +46,6 @@ constexpr int kTab = 64;            // states per B-table chunk
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kF16Scale = 16384.0f;            // 2^14, exact
 
-struct CoefF {
-    float a;    // a - ref_T
-    float al;   // a + l - ref_I   (-inf without internal degrees of freedom)
-    float ux;   // U_x - box centre
-    float uy;   // U_y - box centre
-    float nk;   // -1 / (2 theta)
-};
-
 __device__ __forceinline__ short f2bf(float x) {   // round to nearest even
     uint32_t u = __float_as_uint(x);
     u += 0x7fffu + ((u >> 16) & 1u);

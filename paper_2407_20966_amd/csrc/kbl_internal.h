@@ -69,9 +69,11 @@ bool mixed_tile_fits_2d(int tile, int nx, int ny);
 // tile < 0 (or a tile that does not fit) selects the default for the grid size.
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
+// Bounds backward + gather.  mixed: winners from the FP32 envelopes of the
+// mixed-precision forward (2D only); everything else stays FP64.
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
                                   double* slot, double* grad_states, uint32_t* status, int dim,
-                                  hipStream_t stream);
+                                  bool mixed, hipStream_t stream);
 hipError_t launch_limit_bwd_fp64(const LimitArgs& a, int dim, const double* grad, double* gsol,
                                  double* gbnd, hipStream_t stream);
 

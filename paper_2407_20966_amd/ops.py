@@ -151,11 +151,16 @@ def limit(solution: torch.Tensor, bounds: torch.Tensor, node_weights, n_s: int,
 
 def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor,
                           n_s: int, vgrid: L.VGrid, params: L.Params, solution: torch.Tensor,
-                          node_weights, grad_limited: torch.Tensor, stream=None):
+                          node_weights, grad_limited: torch.Tensor,
+                          fwd_bounds: Optional[torch.Tensor] = None,
+                          fwd_status: Optional[torch.Tensor] = None, stream=None):
     """Gradients of J(limit(solution, bounds(states))) for G = dJ/dlimited.
 
-    Returns (dJ/dstates, dJ/dsolution, dJ/dbounds, status).  The workspace is
-    a torch allocation sized by kbl_backward_workspace_bytes.
+    Returns (dJ/dstates, dJ/dsolution, dJ/dbounds, status).  params.precision
+    selects the forward that is differentiated (FP64 or a mixed form).  The
+    forward's bounds and status may be passed in; otherwise they are
+    recomputed.  The workspace is a torch allocation sized by
+    kbl_backward_workspace_bytes.
     """
     _check(states, "states", torch.float64)
     dev = states.device
@@ -167,6 +172,13 @@ def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torc
     _check(cols, "cols", torch.int32, dev)
     dim = states.shape[0] - 2
     n_elem = rowptr.numel() - 1
+    if (fwd_bounds is None) != (fwd_status is None):
+        raise ValueError("fwd_bounds and fwd_status go together")
+    if fwd_bounds is not None:
+        _check(fwd_bounds, "fwd_bounds", torch.float64, dev)
+        _check(fwd_status, "fwd_status", torch.int32, dev)
+        if tuple(fwd_bounds.shape) != (2 * (dim + 2), n_elem) or fwd_status.numel() != n_elem:
+            raise ValueError("fwd_bounds/fwd_status do not match the element count")
     w = torch.as_tensor(node_weights, dtype=torch.float64).cpu().contiguous()
     nbytes = L.lib().kbl_backward_workspace_bytes(dim, n_elem, int(n_s), cols.numel())
     ws = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=dev)
@@ -176,9 +188,9 @@ def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torc
     status = torch.empty(n_elem, dtype=torch.int32, device=dev)
     rc = L.lib().kbl_bounds_limit_backward(
         C.byref(params), dim, n_elem, int(n_s), cols.numel(), _ptr(states), _ptr(rowptr),
-        _ptr(cols), C.byref(vgrid), _ptr(solution), C.c_void_p(w.data_ptr()),
-        _ptr(grad_limited), _ptr(gst), _ptr(gsol), _ptr(gb), _ptr(status), _ptr(ws),
-        ws.numel(), _stream(dev, stream))
+        _ptr(cols), C.byref(vgrid), _ptr(fwd_bounds), _ptr(fwd_status), _ptr(solution),
+        C.c_void_p(w.data_ptr()), _ptr(grad_limited), _ptr(gst), _ptr(gsol), _ptr(gb),
+        _ptr(status), _ptr(ws), ws.numel(), _stream(dev, stream))
     if rc != L.KBL_OK:
         raise L.KblError(rc, "kbl_bounds_limit_backward")
     return gst, gsol, gb, status
@@ -188,23 +200,26 @@ class KineticBoundsLimit(torch.autograd.Function):
     """limited = limit(solution, bounds(states)) with the hand-written backward.
 
     Gradients flow to `states` (through the kinetic bounds) and to `solution`
-    (through the limiter); nothing from the forward is kept besides the inputs.
+    (through the limiter).  Besides the inputs only the bounds and their
+    status (2(d+2) + 1 numbers per element) are kept; the min/max
+    distributions are recomputed in the backward.
     """
 
     @staticmethod
     def forward(ctx, states, solution, rowptr, cols, n_s, vgrid, params, node_weights):
-        bounds, _ = compute_bounds(states, rowptr, cols, n_s, vgrid, params)
+        bounds, bstatus = compute_bounds(states, rowptr, cols, n_s, vgrid, params)
         limited, _, _ = limit(solution, bounds, node_weights, n_s, params)
-        ctx.save_for_backward(states, solution, rowptr, cols)
+        ctx.save_for_backward(states, solution, rowptr, cols, bounds, bstatus)
         ctx.n_s, ctx.vgrid, ctx.params, ctx.node_weights = n_s, vgrid, params, node_weights
         return limited
 
     @staticmethod
     def backward(ctx, grad_limited):
-        states, solution, rowptr, cols = ctx.saved_tensors
+        states, solution, rowptr, cols, bounds, bstatus = ctx.saved_tensors
         gst, gsol, _, _ = bounds_limit_backward(states, rowptr, cols, ctx.n_s, ctx.vgrid,
                                                 ctx.params, solution, ctx.node_weights,
-                                                grad_limited.contiguous())
+                                                grad_limited.contiguous(), fwd_bounds=bounds,
+                                                fwd_status=bstatus)
         return gst, gsol, None, None, None, None, None, None
 
 

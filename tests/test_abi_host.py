@@ -165,13 +165,15 @@ def test_limit_rejects_bad_params(lib):
     assert _limit(lib, _params(lib), [1.0, 1.0], n_elem=-2) == L.KBL_ERR_ARG
 
 
-def _backward(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20, ws_bytes=None, weights=None):
+def _backward(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20, ws_bytes=None, weights=None,
+              fwd_b=None, fwd_s=None):
     w = np.ones(n_s) if weights is None else np.asarray(weights, dtype=np.float64)
     need = lib.kbl_backward_workspace_bytes(dim, n_elem, n_s, nnz)
     wsb = need if ws_bytes is None else ws_bytes
     return lib.kbl_bounds_limit_backward(C.byref(p), dim, n_elem, n_s, nnz, FAKE, FAKE, FAKE,
-                                         C.byref(g), FAKE, w.ctypes.data_as(C.c_void_p), FAKE,
-                                         FAKE, FAKE, None, None, FAKE, wsb, None)
+                                         C.byref(g), fwd_b, fwd_s, FAKE,
+                                         w.ctypes.data_as(C.c_void_p), FAKE, FAKE, FAKE, None,
+                                         None, FAKE, wsb, None)
 
 
 def test_backward_workspace_size(lib):
@@ -184,7 +186,10 @@ def test_backward_workspace_size(lib):
 def test_backward_rejects_bad_arguments(lib):
     g = _grid()
     assert _backward(lib, _params(lib), g, ws_bytes=16) == L.KBL_ERR_WORKSPACE
-    assert _backward(lib, _params(lib, precision=L.PREC_MIXED_FP16), g) == L.KBL_ERR_UNSUPPORTED
+    assert _backward(lib, _params(lib, precision=7), g) == L.KBL_ERR_UNSUPPORTED
+    assert _backward(lib, _params(lib, precision=L.PREC_MIXED_FP16), _grid(n=(64, 2)),
+                     dim=1, n_s=4) == L.KBL_ERR_UNSUPPORTED
+    assert _backward(lib, _params(lib), g, fwd_b=FAKE, fwd_s=None) == L.KBL_ERR_ARG
     assert _backward(lib, _params(lib, gamma=1.0), g) == L.KBL_ERR_GAMMA
     assert _backward(lib, _params(lib), _grid(n=(65, 48))) == L.KBL_ERR_GRID
     assert _backward(lib, _params(lib), _grid(n=(2049, 2)), dim=1, n_s=4) == L.KBL_ERR_GRID

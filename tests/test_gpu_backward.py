@@ -182,3 +182,47 @@ def test_asymmetric_stencil_flagged(kbl):
     G = np.random.default_rng(2).standard_normal(wl.target.shape)
     _, _, _, st = gpu_backward(kbl, wl, G)
     assert st[7] & kbl.ST_ASYMMETRIC
+
+
+@pytest.mark.parametrize("precision", [0, 3, 2])
+def test_forward_bounds_handover_is_bit_identical(kbl, precision):
+    """Passing the forward's bounds/status gives exactly the recomputed result."""
+    wl = synth.make_quad_workload(N=8, seed=51, grid_nodes=48, name="b_handover")
+    st, tg, rp, cl, vg, _ = dev_inputs(kbl, wl)
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=precision)
+    G = torch.from_numpy(np.random.default_rng(4).standard_normal(wl.target.shape)).to(st.device)
+    a = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm, tg, wl.node_weights, G)
+    b0, s0 = kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm)
+    b = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm, tg, wl.node_weights, G,
+                                  fwd_bounds=b0, fwd_status=s0)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("precision,name", [(3, "fp32"), (2, "fp16"), (1, "bf16")])
+def test_mixed_backward_error_vs_fp64(kbl, precision, name):
+    """Gradient of the mixed-precision forward (FP32 envelope winners, limiter
+    on the mixed bounds) against the FP64 gradient: reported, and bounded
+    loosely (the limiter's ratio terms amplify the 1e-7 bound differences)."""
+    wl = synth.make_quad_workload(N=32, seed=52, grid_nodes=48, name="b_mixed")
+    st, tg, rp, cl, vg, prm = dev_inputs(kbl, wl)
+    prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=precision)
+    G = torch.zeros_like(st)
+    G[0] = torch.from_numpy(np.random.default_rng(5).standard_normal(wl.n_nodes)).to(st.device)
+    ref = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm, tg, wl.node_weights, G)
+    mix = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm_m, tg, wl.node_weights, G)
+    again = kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, prm_m, tg, wl.node_weights, G)
+    torch.cuda.synchronize()
+    g_ref = (ref[0] + ref[1]).cpu().numpy()
+    g_mix = (mix[0] + mix[1]).cpu().numpy()
+    scale = np.abs(g_ref).max()
+    err = np.abs(g_mix - g_ref)
+    share = (err <= 1e-6 * scale).mean()
+    print(f"[bwd-mixed] {name}: max err {err.max() / scale:.2e}, p99 "
+          f"{np.quantile(err, 0.99) / scale:.2e} of the max gradient; "
+          f"{100 * share:.1f}% of DoFs within 1e-6", flush=True)
+    assert err.max() <= 5e-2 * scale
+    assert share >= 0.9
+    for x, y in zip(mix, again):
+        assert torch.equal(x, y)
