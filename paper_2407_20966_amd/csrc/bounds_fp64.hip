@@ -14,13 +14,16 @@
 //     monotone, min_i g_i = exp(min_i q_i) (eq. fminmax), and likewise for the
 //     internal part g_I = (theta delta / 2) g (Sec. 3.6): four running extrema
 //     per node stay in registers and only four exp per node are taken at the
-//     end.  (A tile variant reads B from an LDS table instead.)
+//     end.  (Tile variants read B, or A and B, from LDS tables instead.)
 //  3. Relaxation (eq. relaxed), trapezoid weights (Sec. 3.7) and the moment
 //     contraction (eq. rhobounds, Ebounds, mmbounds, mpbounds) are done per
 //     node, then reduced across the workgroup in a fixed order (bitwise
 //     deterministic), floored (Sec. 3.8) and stored.
 // Each thread owns a TX x TY tile of velocity nodes, strided by 16 so that
-// the LDS table reads of a wave are contiguous or broadcast.
+// the LDS table reads of a wave are contiguous or broadcast.  Tile modes:
+// BTAB = 0 computes A and B per state in registers; 1 reads B from a table
+// built per chunk of states; 2 reads A, A + ln(theta delta / 2) and B from
+// such tables (per state: a few LDS reads instead of 4 TX + 3 TY VALU ops).
 // Inputs are validated before the hot loop, which therefore never sees a NaN
 // (only finite values and -inf when delta = 0).
 #include "bounds_common.h"
@@ -30,16 +33,20 @@ namespace {
 
 // ---------------------------------------------------------------- 2D kernel
 // BX x BY threads; thread (tx, ty) owns velocity nodes (tx + BX i, ty + BY j),
-// i < TX, j < TY.  BTAB = 1 reads B from an LDS table built per sub-chunk of
-// kTabStates states (fewer VALU ops, more LDS traffic and barriers).
+// i < TX, j < TY.  BTAB = 1 reads B (and BTAB = 2 also A, A + l) from LDS
+// tables built per sub-chunk of kTabStates states (fewer VALU ops, more LDS
+// traffic and barriers).
 template <int BX, int BY, int TX, int TY, int BTAB>
 __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
     constexpr int NT = BX * BY;
+    constexpr int NXM = BX * TX;
     constexpr int NYM = BY * TY;
     constexpr int kTabStates = 32;
     static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
     __shared__ Coef sC[kMaxStates];
     __shared__ double sB[BTAB ? kTabStates : 1][BTAB ? NYM : 1];
+    // BTAB = 2: A and A + l tables too (row 2s: A, row 2s+1: A + l)
+    __shared__ double sA[BTAB == 2 ? 2 * kTabStates : 1][BTAB == 2 ? NXM : 1];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
@@ -97,23 +104,43 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
                         const double d = (loy + jc * hy) - sC[t0 + s].uy;
                         sB[s][j] = (sC[t0 + s].nk * d) * d;
                     }
+                    if (BTAB == 2) {
+                        for (int idx = tid; idx < tn * NXM; idx += NT) {
+                            const int s = idx / NXM, i = idx - s * NXM;
+                            const int ic = i < p.nx ? i : p.nx - 1;
+                            const Coef& c = sC[t0 + s];
+                            const double d = (lox + ic * hx) - c.ux;
+                            const double t = c.nk * d;
+                            sA[2 * s][i] = fma(t, d, c.a);
+                            sA[2 * s + 1][i] = fma(t, d, c.al);
+                        }
+                    }
                     __syncthreads();
                 }
 #pragma unroll 2
                 for (int s = 0; s < tn; ++s) {
-                    const Coef c = sC[t0 + s];
                     double a[TX], ai[TX], b[TY];
+                    if (BTAB == 2) {
 #pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const double d = ux[i] - c.ux;
-                        const double t = c.nk * d;
-                        a[i] = fma(t, d, c.a);
-                        ai[i] = fma(t, d, c.al);
+                        for (int i = 0; i < TX; ++i) {
+                            a[i] = sA[2 * s][tx + BX * i];
+                            ai[i] = sA[2 * s + 1][tx + BX * i];
+                        }
+                    } else {
+                        const Coef c = sC[t0 + s];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) {
+                            const double d = ux[i] - c.ux;
+                            const double t = c.nk * d;
+                            a[i] = fma(t, d, c.a);
+                            ai[i] = fma(t, d, c.al);
+                        }
                     }
                     if (BTAB) {
 #pragma unroll
                         for (int j = 0; j < TY; ++j) b[j] = sB[s][ty + BY * j];
                     } else {
+                        const Coef c = sC[t0 + s];
 #pragma unroll
                         for (int j = 0; j < TY; ++j) {
                             const double d = uy[j] - c.uy;
@@ -272,16 +299,23 @@ constexpr Tile2D kTiles2D[] = {
     KBL_TILE(32, 8, 2, 8, 1),    // 7: n <= 64, B from LDS
     KBL_TILE(16, 16, 2, 4, 0),   // 8: nx <= 32, ny <= 64
     KBL_TILE(16, 16, 4, 2, 0),   // 9: nx <= 64, ny <= 32
+    KBL_TILE(16, 16, 2, 2, 2),   // 10: n <= 32, A and B from LDS
+    KBL_TILE(16, 16, 3, 3, 2),   // 11: n <= 48, A and B from LDS
+    KBL_TILE(16, 16, 4, 4, 2),   // 12: n <= 64, A and B from LDS
+    KBL_TILE(16, 8, 3, 6, 2),    // 13: n <= 48, two waves, A and B from LDS
 };
 #undef KBL_TILE
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
 
+// Defaults from a measured sweep: with A, A + l and B read from LDS tables
+// the inner loop is the pair work alone (tiles 11 and 12); kbl_autotune_bounds
+// may still pick another tile or a persistent grid for a given shape.
 int default_tile_2d(int nx, int ny) {
     const int n = nx > ny ? nx : ny;
     if (n <= 16) return 0;
     if (n <= 32) return 1;
-    if (n <= 48) return 3;
-    return 5;
+    if (n <= 48) return 11;
+    return 12;
 }
 
 }  // namespace

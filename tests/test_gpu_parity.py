@@ -228,3 +228,20 @@ def test_limiter_alone_on_oracle_bounds(kbl):
     lerr, _ = limited_error(lim, rl, scale, wl.n_s)
     assert lerr <= TOL
     assert np.array_equal(ls, rls)
+
+
+# every FP64 2D tile configuration (forced through the tuning knob), each on a
+# ragged grid that leaves some of its threads' nodes outside the grid
+FP64_TILE_EXTENTS = {0: (16, 16), 1: (32, 32), 2: (48, 48), 3: (48, 48), 4: (48, 48),
+                     5: (64, 64), 6: (64, 64), 7: (64, 64), 8: (32, 64), 9: (64, 32),
+                     10: (32, 32), 11: (48, 48), 12: (64, 64), 13: (48, 48)}
+
+
+@pytest.mark.parametrize("tile", sorted(FP64_TILE_EXTENTS))
+def test_every_fp64_tile(kbl, monkeypatch, tile):
+    mx, my = FP64_TILE_EXTENTS[tile]
+    n = (mx - 3, my - 2)
+    wl = synth.make_quad_workload(N=6, seed=300 + tile, grid_nodes=n[0], name=f"quad_tile{tile}")
+    wl.grid = GridSpec(GRID_STENCIL, n, k=4.0)
+    monkeypatch.setenv("KBL_BOUNDS_TILE", str(tile))
+    check_workload(kbl, wl)
