@@ -62,10 +62,11 @@ def _load():
         P = C.c_void_p
         lib.oracle_bounds.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
                                       C.c_int, P, P, P, C.c_double,
-                                      C.c_int64, C.c_int, C.c_int64, P, P, P, P, C.c_int64, P, P]
+                                      C.c_int64, C.c_int64, C.c_int, C.c_int64, P, P, P, P,
+                                      C.c_int64, C.c_int, P, P]
         lib.oracle_bounds.restype = C.c_int
         lib.oracle_limit.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double,
-                                     C.c_int64, C.c_int, P, P, P, P, C.c_int64, P, P, P]
+                                     C.c_int64, C.c_int, P, P, P, C.c_int, P, C.c_int64, P, P, P]
         lib.oracle_limit.restype = C.c_int
         lib.oracle_backward.argtypes = [C.c_int, C.c_double, C.c_double, C.c_double, C.c_double,
                                         C.c_double, C.c_int, P, P, P, C.c_double, C.c_int64,
@@ -85,14 +86,22 @@ def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
            cols: np.ndarray, n_s: int, grid_mode: int, n, lo=(0.0, 0.0),
            hi=(0.0, 0.0), k: float = 4.0, r_fac: float = 1e-3,
            rho_floor: float = RHO_FLOOR,
-           elems: Optional[np.ndarray] = None) -> Tuple[np.ndarray, np.ndarray]:
-    """Kinetic bounds [2(d+2), n_sel] and status [n_sel] (Sec. 3.3-3.8)."""
+           elems: Optional[np.ndarray] = None, energy_mode: int = 0,
+           n_src: Optional[int] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """Kinetic bounds [2(d+2), n_sel] and status [n_sel] (Sec. 3.3-3.8).
+
+    cols list source units of n_s nodes each: elements (n_src = n_elem, the
+    default) or, with n_s = 1, single nodes of a node-level stencil.
+    energy_mode 0: separate g_T / g_I envelopes; 1: per-state energy integrand.
+    """
     lib = _load()
     states = np.ascontiguousarray(states, dtype=np.float64)
     rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
     cols = np.ascontiguousarray(cols, dtype=np.int32)
     n_elem = rowptr.size - 1
-    assert states.shape == (dim + 2, n_elem * n_s)
+    if n_src is None:
+        n_src = n_elem
+    assert states.shape == (dim + 2, n_src * n_s)
     if elems is not None:
         elems = np.ascontiguousarray(elems, dtype=np.int64)
         n_sel = elems.size
@@ -104,8 +113,8 @@ def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
     out = np.empty((2 * (dim + 2), n_sel), dtype=np.float64)
     st = np.empty(n_sel, dtype=np.uint32)
     rc = lib.oracle_bounds(dim, gamma, r_fac, rho_floor, grid_mode, _p(n_arr), _p(lo_arr),
-                           _p(hi_arr), k, n_elem, n_s, cols.size, _p(states), _p(rowptr), _p(cols),
-                           _p(elems), n_sel, _p(out), _p(st))
+                           _p(hi_arr), k, n_elem, n_src, n_s, cols.size, _p(states), _p(rowptr),
+                           _p(cols), _p(elems), n_sel, energy_mode, _p(out), _p(st))
     if rc != 0:
         raise ValueError("oracle_bounds rejected its arguments")
     return out, st
@@ -113,8 +122,11 @@ def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
 
 def limit(dim: int, gamma: float, solution: np.ndarray, bounds_sel: np.ndarray,
           node_weights: np.ndarray, n_s: int, p_floor: float = P_FLOOR,
-          eps: float = EPS_ALPHA, elems: Optional[np.ndarray] = None):
-    """Squeeze limiter + pressure step (Sec. 3.4, 3.8).
+          eps: float = EPS_ALPHA, elems: Optional[np.ndarray] = None,
+          independent: bool = False):
+    """Squeeze limiter + pressure step (Sec. 3.4, 3.8); coupled alpha_min, or
+    per-component alpha_i with ``independent``.  Weights may be zero (nodes
+    outside the mean, e.g. flux points) but must have a positive sum.
 
     Returns (limited [d+2, n_sel*n_s], alpha [2, n_sel], status [n_sel]).
     ``bounds_sel`` holds one column per selected element.
@@ -134,7 +146,8 @@ def limit(dim: int, gamma: float, solution: np.ndarray, bounds_sel: np.ndarray,
     al = np.empty((2, n_sel), dtype=np.float64)
     st = np.empty(n_sel, dtype=np.uint32)
     rc = lib.oracle_limit(dim, gamma, p_floor, eps, n_elem, n_s, _p(solution), _p(bounds_sel),
-                          _p(c), _p(elems), n_sel, _p(lim), _p(al), _p(st))
+                          _p(c), int(bool(independent)), _p(elems), n_sel, _p(lim), _p(al),
+                          _p(st))
     if rc != 0:
         raise ValueError("oracle_limit rejected its arguments")
     return lim, al, st
@@ -178,13 +191,14 @@ def delta(dim: int, gamma: float) -> float:
     return _load().oracle_delta(dim, gamma)
 
 
-def workload_bounds(wl, elems=None, r_fac=None):
+def workload_bounds(wl, elems=None, r_fac=None, energy_mode=0):
     """Convenience: bounds of a synth.Workload (or a selection of its elements)."""
     g = wl.grid
     return bounds(wl.dim, wl.gamma, wl.states, wl.rowptr, wl.cols, wl.n_s, g.mode,
                   g.n[: wl.dim], g.lo, g.hi, g.k, wl.r_fac if r_fac is None else r_fac,
-                  elems=elems)
+                  elems=elems, energy_mode=energy_mode)
 
 
-def workload_limit(wl, bounds_sel, elems=None):
-    return limit(wl.dim, wl.gamma, wl.target, bounds_sel, wl.node_weights, wl.n_s, elems=elems)
+def workload_limit(wl, bounds_sel, elems=None, independent=False):
+    return limit(wl.dim, wl.gamma, wl.target, bounds_sel, wl.node_weights, wl.n_s, elems=elems,
+                 independent=independent)

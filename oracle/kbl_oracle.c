@@ -17,14 +17,20 @@
  *   - the internal-energy part follows the reduced-distribution model of
  *     Sec. 3.6: g_I = (theta delta / 2) g_T with delta = 2/(gamma-1) - d, and
  *     f_I gets its own min/max envelope (the transported-scalar reading);
+ *     optionally (energy_mode 1) the energy integrand is taken per state
+ *     instead, min/max over i of g_i (|u|^2/2 + theta_i delta/2);
  *   - moments use a uniform trapezoid rule on a Cartesian velocity grid
  *     (Sec. 3.7) over a global box or the per-stencil box of eq. truncdomain
  *     (upper end read as max(U + k sqrt(theta)), i.e. k standard deviations
  *     on both sides);
  *   - sums are Neumaier-compensated;
  *   - the limiter is the coupled squeeze limiter of Sec. 3.4 (eq. alpha,
- *     eq. limiter, epsilon rule), followed by the pressure step of Sec. 3.8
- *     (eq. pmin, eq. doublelimit).
+ *     eq. limiter, epsilon rule), or its independent per-component form
+ *     described there, followed by the pressure step of Sec. 3.8 (eq. pmin,
+ *     eq. doublelimit);
+ *   - a stencil lists source units: elements (n_s nodes each) or single
+ *     nodes (n_s = 1), so node-level stencils such as the solution and
+ *     flux points of Sec. 5 use the same code.
  * OpenMP parallelises over elements only; every element is computed by one
  * thread from start to end.
  */
@@ -104,16 +110,16 @@ static double maxwellian(int d, const prim_t* s, const double* u) {
 static unsigned element_bounds(int d, double gamma, double r_fac, double rho_floor,
                                int grid_mode, const int* n, const double* lo_in,
                                const double* hi_in, double k, int n_s,
-                               const double* states, int64_t n_elem, int64_t nnz,
+                               const double* states, int64_t n_src, int64_t nnz,
                                const int* rowptr, const int* cols, int64_t e,
-                               double* out) {
+                               int energy_mode, double* out) {
     const int nv = d + 2;
-    const int64_t n_nodes = n_elem * n_s;
+    const int64_t n_nodes = n_src * n_s;
     const int row0 = rowptr[e], row1 = rowptr[e + 1];
-    /* a row must be non-empty, inside [0, nnz] and name existing elements */
+    /* a row must be non-empty, inside [0, nnz] and name existing source units */
     int bad_row = (row0 < 0 || row1 <= row0 || row1 > nnz);
     for (int r = row0; !bad_row && r < row1; ++r)
-        if (cols[r] < 0 || cols[r] >= n_elem) bad_row = 1;
+        if (cols[r] < 0 || cols[r] >= n_src) bad_row = 1;
     if (bad_row) {
         for (int v = 0; v < 2 * nv; ++v) out[v] = NAN;
         return OR_ST_BAD_STENCIL;
@@ -170,27 +176,38 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
             /* Step 2 of Sec. 3.9: min/max distribution over the stencil
              * (eq. fminmax) for the translational part g and the internal
              * part g_I = (theta delta/2) g (Sec. 3.6). */
+            double half_u2 = 0.0;
+            for (int j = 0; j < d; ++j) half_u2 += 0.5 * u[j] * u[j];
             double fTmin = INFINITY, fTmax = -INFINITY, fImin = INFINITY, fImax = -INFINITY;
+            double eAmin = INFINITY, eAmax = -INFINITY;   /* per-state energy integrand */
             for (int i = 0; i < S; ++i) {
                 double g = maxwellian(d, &st[i], u);
                 double gI = 0.5 * st[i].theta * delta * g;
+                double eA = g * (half_u2 + 0.5 * st[i].theta * delta);
                 if (g < fTmin) fTmin = g;
                 if (g > fTmax) fTmax = g;
                 if (gI < fImin) fImin = gI;
                 if (gI > fImax) fImax = gI;
+                if (eA < eAmin) eAmin = eA;
+                if (eA > eAmax) eAmax = eA;
             }
             /* Relaxation of the envelopes (eq. relaxed). */
-            fTmin *= (1.0 - r_fac); fImin *= (1.0 - r_fac);
-            fTmax *= (1.0 + r_fac); fImax *= (1.0 + r_fac);
+            fTmin *= (1.0 - r_fac); fImin *= (1.0 - r_fac); eAmin *= (1.0 - r_fac);
+            fTmax *= (1.0 + r_fac); fImax *= (1.0 + r_fac); eAmax *= (1.0 + r_fac);
 
-            double half_u2 = 0.0;
-            for (int j = 0; j < d; ++j) half_u2 += 0.5 * u[j] * u[j];
             /* Density and energy: non-negative invariants (eq. rhobounds, Ebounds),
-             * energy invariant extended by the internal part (Sec. 3.6). */
+             * energy invariant extended by the internal part (Sec. 3.6): either
+             * separate envelopes of g_T and g_I, or the envelope of the
+             * per-state energy integrand. */
             nsum_add(&rmin, M * fTmin);
             nsum_add(&rmax, M * fTmax);
-            nsum_add(&emin, M * (half_u2 * fTmin + fImin));
-            nsum_add(&emax, M * (half_u2 * fTmax + fImax));
+            if (energy_mode == 1) {
+                nsum_add(&emin, M * eAmin);
+                nsum_add(&emax, M * eAmax);
+            } else {
+                nsum_add(&emin, M * (half_u2 * fTmin + fImin));
+                nsum_add(&emax, M * (half_u2 * fTmax + fImax));
+            }
             /* Momentum: split by the sign of u_j (eq. mmbounds, mpbounds). */
             for (int j = 0; j < d; ++j) {
                 if (u[j] < 0.0) {
@@ -216,21 +233,24 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
 
 /*
  * Bounds for a selection of elements.
- *   states  [d+2][n_elem*n_s] conserved variables, SoA, element-major nodes
- *   rowptr  [n_elem+1], cols[nnz]: element stencils (element ids); bad rows
- *           are flagged OR_ST_BAD_STENCIL with NaN bounds
+ *   states  [d+2][n_src*n_s] conserved variables, SoA, unit-major nodes
+ *   rowptr  [n_elem+1], cols[nnz]: stencils listing source units (elements of
+ *           n_s nodes, or single nodes with n_s = 1); bad rows are flagged
+ *           OR_ST_BAD_STENCIL with NaN bounds
  *   elems   [n_sel] element ids to evaluate (NULL: all, n_sel = n_elem)
+ *   energy_mode 0: separate g_T / g_I envelopes; 1: per-state integrand
  *   bounds  out [2(d+2)][n_sel]: rows (rho, m.., E)_min then (rho, m.., E)_max
  *   status  out [n_sel] or NULL
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
                   int grid_mode, const int* n, const double* lo, const double* hi, double k,
-                  int64_t n_elem, int n_s, int64_t nnz, const double* states,
+                  int64_t n_elem, int64_t n_src, int n_s, int64_t nnz, const double* states,
                   const int* rowptr, const int* cols,
-                  const int64_t* elems, int64_t n_sel,
+                  const int64_t* elems, int64_t n_sel, int energy_mode,
                   double* bounds, unsigned* status) {
     if (d < 1 || d > 2 || n_s < 1 || !(gamma > 1.0)) return -1;
+    if (energy_mode != 0 && energy_mode != 1) return -1;
     for (int j = 0; j < d; ++j) if (n[j] < 2) return -1;
     if (oracle_delta(d, gamma) < 0.0) return -1;
     const int nv = d + 2;
@@ -239,7 +259,7 @@ int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
         int64_t e = elems ? elems[q] : q;
         double out[2 * OR_MAXV];
         unsigned st = element_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k,
-                                     n_s, states, n_elem, nnz, rowptr, cols, e, out);
+                                     n_s, states, n_src, nnz, rowptr, cols, e, energy_mode, out);
         for (int v = 0; v < 2 * nv; ++v) bounds[(int64_t)v * n_sel + q] = out[v];
         if (status) status[q] = st;
     }
@@ -249,13 +269,16 @@ int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
 /* ------------------------------------------------------------------ limiter */
 
 /*
- * Coupled squeeze limiter (Sec. 3.4) and pressure step (Sec. 3.8) of one
- * element.  w[v*n_s + j]: the element's nodal solution; b: its bounds;
- * out: limited nodal solution; alpha[0] = alpha_min, alpha[1] = alpha_P.
+ * Squeeze limiter (Sec. 3.4) and pressure step (Sec. 3.8) of one element.
+ * w[v*n_s + j]: the element's nodal values (V); b: its bounds; c: mean
+ * weights (zero for nodes that do not enter the mean, e.g. flux points);
+ * out: limited nodal values; alpha[0] = alpha_min, alpha[1] = alpha_P.
+ * independent = 0: every component blended with alpha_min (eq. limiter);
+ * 1: each component blended with its own alpha_i.
  */
 static unsigned element_limit(int d, double gamma, double p_floor, double eps, int n_s,
                               const double* w, const double* b, const double* c,
-                              double* out, double* alpha) {
+                              int independent, double* out, double* alpha) {
     const int nv = d + 2;
     unsigned status = 0;
     for (int v = 0; v < 2 * nv; ++v)
@@ -279,7 +302,7 @@ static unsigned element_limit(int d, double gamma, double p_floor, double eps, i
         if (wbar[v] < b[v] || wbar[v] > b[nv + v]) status |= OR_ST_MEAN_OUTSIDE;
 
     /* Limiting factor per component (eq. alpha) with the epsilon rule. */
-    double amin = 1.0;
+    double amin = 1.0, acomp[OR_MAXV];
     for (int v = 0; v < nv; ++v) {
         double wmax = -INFINITY, wmin = INFINITY;
         for (int j = 0; j < n_s; ++j) {
@@ -296,14 +319,17 @@ static unsigned element_limit(int d, double gamma, double p_floor, double eps, i
             if (ru < av) av = ru;
             if (rl < av) av = rl;
         }
+        acomp[v] = av;
         if (av < amin) amin = av;
     }
     if (amin < 1.0) status |= OR_ST_LIMITED;
 
-    /* Coupled blend towards the mean (eq. limiter). */
-    for (int v = 0; v < nv; ++v)
+    /* Blend towards the mean: coupled (eq. limiter) or per component. */
+    for (int v = 0; v < nv; ++v) {
+        const double a = independent ? acomp[v] : amin;
         for (int j = 0; j < n_s; ++j)
-            out[v * n_s + j] = wbar[v] + amin * (w[v * n_s + j] - wbar[v]);
+            out[v * n_s + j] = wbar[v] + a * (w[v * n_s + j] - wbar[v]);
+    }
 
     /* Pressure step (eq. pmin, eq. doublelimit). */
     double pmin = INFINITY;
@@ -332,16 +358,22 @@ static unsigned element_limit(int d, double gamma, double p_floor, double eps, i
 /*
  * Limit a selection of elements.
  *   solution [d+2][n_elem*n_s]; bounds [2(d+2)][n_sel] (one column per
- *   selected element); c [n_s] positive weights;
+ *   selected element); c [n_s] non-negative weights with a positive sum;
+ *   independent: per-component blending instead of the coupled minimum;
  *   limited out [d+2][n_sel*n_s]; alpha out [2][n_sel]; status out [n_sel].
  */
 int oracle_limit(int d, double gamma, double p_floor, double eps,
                  int64_t n_elem, int n_s, const double* solution,
-                 const double* bounds, const double* c,
+                 const double* bounds, const double* c, int independent,
                  const int64_t* elems, int64_t n_sel,
                  double* limited, double* alpha, unsigned* status) {
     if (d < 1 || d > 2 || n_s < 1 || n_s > 4096 || !(gamma > 1.0)) return -1;
-    for (int j = 0; j < n_s; ++j) if (!(c[j] > 0.0)) return -1;
+    double csum = 0.0;
+    for (int j = 0; j < n_s; ++j) {
+        if (!(c[j] >= 0.0) || !isfinite(c[j])) return -1;
+        csum += c[j];
+    }
+    if (!(csum > 0.0)) return -1;
     const int nv = d + 2;
     const int64_t n_nodes = n_elem * n_s;
 #pragma omp parallel for schedule(static)
@@ -353,7 +385,7 @@ int oracle_limit(int d, double gamma, double p_floor, double eps,
         for (int v = 0; v < nv; ++v)
             for (int j = 0; j < n_s; ++j) w[v * n_s + j] = solution[(int64_t)v * n_nodes + e * n_s + j];
         for (int v = 0; v < 2 * nv; ++v) b[v] = bounds[(int64_t)v * n_sel + q];
-        unsigned st = element_limit(d, gamma, p_floor, eps, n_s, w, b, c, o, al);
+        unsigned st = element_limit(d, gamma, p_floor, eps, n_s, w, b, c, independent, o, al);
         for (int v = 0; v < nv; ++v)
             for (int j = 0; j < n_s; ++j) limited[(int64_t)v * n_sel * n_s + q * n_s + j] = o[v * n_s + j];
         alpha[q] = al[0];
@@ -542,7 +574,7 @@ static void element_bounds_backward(int d, double gamma, double r_fac, double rh
     /* recompute rho_min to know whether the floor was active */
     double out[2 * OR_MAXV];
     element_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo_in, hi_in, k, n_s, states,
-                   n_elem, rowptr[n_elem], rowptr, cols, e, out);
+                   n_elem, rowptr[n_elem], rowptr, cols, e, 0, out);
     if (out[0] == rho_floor) gb[0] = 0.0;
     const double delta = oracle_delta(d, gamma);
 
@@ -674,8 +706,8 @@ int oracle_backward(int d, double gamma, double r_fac, double rho_floor, double 
     for (int64_t i = 0; i < (int64_t)nv * n_nodes; ++i) gstates[i] = 0.0;
     double* bnd = (double*)malloc(sizeof(double) * 2 * nv * (size_t)(n_elem > 0 ? n_elem : 1));
     unsigned* st = (unsigned*)malloc(sizeof(unsigned) * (size_t)(n_elem > 0 ? n_elem : 1));
-    oracle_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k, n_elem, n_s,
-                  rowptr[n_elem], states, rowptr, cols, NULL, n_elem, bnd, st);
+    oracle_bounds(d, gamma, r_fac, rho_floor, grid_mode, n, lo, hi, k, n_elem, n_elem, n_s,
+                  rowptr[n_elem], states, rowptr, cols, NULL, n_elem, 0, bnd, st);
     double w[OR_MAXV * 64], g[OR_MAXV * 64], gw[OR_MAXV * 64], b[2 * OR_MAXV], gb[2 * OR_MAXV];
     for (int64_t e = 0; e < n_elem; ++e) {
         for (int v = 0; v < nv; ++v)
