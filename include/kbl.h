@@ -89,8 +89,18 @@ typedef struct {
     double  p_floor;    /* pressure floor of the pressure step (Sec. 3.8; 1e-12) */
     double  eps_alpha;  /* epsilon of the limiter's degenerate-range rule (Sec. 3.4; 1e-13) */
     int32_t precision;  /* KBL_PREC_* (kbl_compute_bounds only) */
-    int32_t reserved;   /* must be 0 */
+    int32_t flags;      /* KBL_FLAG_* bits, 0 for the paper's default method */
 } kbl_params;
+
+/* kbl_params.flags */
+/* kbl_limit: limit each component with its own alpha_i instead of the coupled
+ * minimum (the independent option of Sec. 3.4).  alpha[0] still reports
+ * min_i alpha_i. */
+#define KBL_FLAG_INDEPENDENT_ALPHA 0x1
+/* kbl_compute_bounds(_nodes), FP64 only: energy bounds from the envelope of
+ * the per-state energy integrand g_i (|u|^2/2 + theta_i delta/2) instead of
+ * separate envelopes of g_T and g_I = (theta delta/2) g_T (Sec. 3.6). */
+#define KBL_FLAG_ENERGY_PERSTATE 0x2
 
 /* Fills `p` with the paper's defaults for the given gamma (r_fac 1e-3, floors
  * 1e-12, epsilon 1e-13, FP64). */
@@ -120,13 +130,33 @@ void kbl_default_params(kbl_params* p, double gamma);
  * accumulation) or on the FP32 VALU; the admissibility checks, velocity box,
  * exp scaling, relaxation and floors stay FP64.  Results agree with the FP64
  * path to about 1e-6 relative (momentum relative to the stencil's momentum
- * scale).
+ * scale).  With KBL_FLAG_ENERGY_PERSTATE (FP64 only) the energy rows come
+ * from the per-state energy integrand instead.
  */
 kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_elem,
                               int32_t n_s, int64_t nnz, const double* states,
                               const int32_t* rowptr, const int32_t* cols,
                               const kbl_vgrid* vgrid, double* bounds,
                               uint32_t* elem_status, void* stream);
+
+/*
+ * kbl_compute_bounds_nodes - the same bounds for node-level stencils: row e
+ * lists node ids, and each listed node is one stencil state.  This is the
+ * stencil of Sec. 5 (the element's solution points, its own flux points and
+ * the neighbours' flux points on the shared faces), or any other set of
+ * nodes, e.g. per-node neighbourhoods.
+ *
+ *   states       [d+2][n_nodes] FP64 conserved states of every node that a
+ *                stencil may list (solution and flux points alike).
+ *   rowptr, cols node stencil in CSR form; ids outside [0, n_nodes) give
+ *                KBL_ST_BAD_STENCIL and NaN bounds.
+ *   the rest     as in kbl_compute_bounds (launch choices as for n_s = 1).
+ */
+kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64_t n_elem,
+                                    int64_t n_nodes, int64_t nnz, const double* states,
+                                    const int32_t* rowptr, const int32_t* cols,
+                                    const kbl_vgrid* vgrid, double* bounds,
+                                    uint32_t* elem_status, void* stream);
 
 /*
  * kbl_autotune_bounds - picks the launch configuration of kbl_compute_bounds
@@ -158,14 +188,18 @@ void kbl_autotune_clear(void);
  *
  *   solution     [d+2][n_elem*n_s] nodal solution to limit.
  *   bounds       [2(d+2)][n_elem] as written by kbl_compute_bounds.
- *   node_weights HOST pointer, n_s positive weights c_j of the element mean
- *                (Assumption (iii)(a) of Sec. 4); copied during the call.
+ *   node_weights HOST pointer, n_s weights c_j of the element mean
+ *                (Assumption (iii)(a) of Sec. 4), copied during the call:
+ *                non-negative with a positive sum; nodes of V that are not
+ *                quadrature nodes of the mean (flux points) take weight 0.
  *   limited      out [d+2][n_elem*n_s]; may alias `solution`.
  *   alpha        out [2][n_elem] (alpha_min, alpha_P; alpha_P = 1 when the
  *                pressure step does not fire) or NULL.
  *   elem_status  out [n_elem] or NULL.
- * n_s must be at most 64.  When P(mean) <= p_floor the pressure step uses
- * alpha_P = 0.  Non-finite bounds leave the element unchanged.
+ * n_s (nodes of V per element) must be at most 64.  When P(mean) <= p_floor
+ * the pressure step uses alpha_P = 0.  Non-finite bounds leave the element
+ * unchanged.  KBL_FLAG_INDEPENDENT_ALPHA blends each component with its own
+ * alpha_i instead of the coupled minimum.
  */
 kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
                      const double* solution, const double* bounds,
@@ -216,7 +250,8 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
  *   elem_status  out [n_elem] forward bounds status plus KBL_ST_ASYMMETRIC /
  *                KBL_ST_TOO_LARGE, or NULL.
  *   workspace    device memory of at least kbl_backward_workspace_bytes().
- * Stencils of more than 256 states contribute no state gradient
+ * Element-level stencils and params->flags == 0 only (KBL_ERR_UNSUPPORTED
+ * otherwise).  Stencils of more than 256 states contribute no state gradient
  * (KBL_ST_TOO_LARGE).  Grids: up to 64 x 64 (d = 2), 2048 nodes (d = 1).
  * The result is bitwise deterministic.
  */

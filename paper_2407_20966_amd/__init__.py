@@ -14,8 +14,8 @@ from ._lib import (  # noqa: F401
 )
 from .ops import (  # noqa: F401
     KineticBoundsLimit, autotune_bounds, bounds_and_limit, bounds_limit_backward,
-    compute_bounds, limit, make_params, make_vgrid,
+    compute_bounds, compute_bounds_nodes, limit, make_params, make_vgrid,
 )
 
-__all__ = ["compute_bounds", "limit", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
+__all__ = ["compute_bounds", "compute_bounds_nodes", "limit", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
            "KineticBoundsLimit", "make_params", "make_vgrid", "KblError"]

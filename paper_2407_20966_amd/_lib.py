@@ -25,6 +25,8 @@ PREC_FP64 = 0
 PREC_MIXED_BF16 = 1
 PREC_MIXED_FP16 = 2
 PREC_MIXED_FP32 = 3
+FLAG_INDEPENDENT_ALPHA = 0x1
+FLAG_ENERGY_PERSTATE = 0x2
 
 ST_INADMISSIBLE = 0x1
 ST_RHO_FLOOR = 0x2
@@ -47,7 +49,7 @@ class VGrid(C.Structure):
 class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("r_fac", C.c_double), ("rho_floor", C.c_double),
                 ("p_floor", C.c_double), ("eps_alpha", C.c_double), ("precision", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("flags", C.c_int32)]
 
 
 class KblError(RuntimeError):
@@ -86,6 +88,10 @@ def _load():
         lib.kbl_limit.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
                                   P, P, P, P, P, P, P]
         lib.kbl_limit.restype = C.c_int
+        lib.kbl_compute_bounds_nodes.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64,
+                                                 C.c_int64, C.c_int64, P, P, P, C.POINTER(VGrid),
+                                                 P, P, P]
+        lib.kbl_compute_bounds_nodes.restype = C.c_int
         lib.kbl_autotune_bounds.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
                                             C.c_int64, P, P, P, C.POINTER(VGrid), P, P,
                                             C.c_int64, P]

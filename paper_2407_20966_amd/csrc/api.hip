@@ -25,8 +25,10 @@ bool internal_dof(int dim, double gamma, double* half_delta) {
     return true;
 }
 
+constexpr int32_t kKnownFlags = KBL_FLAG_INDEPENDENT_ALPHA | KBL_FLAG_ENERGY_PERSTATE;
+
 kbl_status check_params(const kbl_params* p, int32_t dim, double* half_delta) {
-    if (!p || (dim != 1 && dim != 2) || p->reserved != 0) return KBL_ERR_ARG;
+    if (!p || (dim != 1 && dim != 2) || (p->flags & ~kKnownFlags) != 0) return KBL_ERR_ARG;
     if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return KBL_ERR_GAMMA;
     if (!internal_dof(dim, p->gamma, half_delta)) return KBL_ERR_GAMMA;
     if (!(p->r_fac >= 0.0 && p->r_fac < 1.0)) return KBL_ERR_ARG;
@@ -37,17 +39,17 @@ kbl_status check_params(const kbl_params* p, int32_t dim, double* half_delta) {
 }
 
 // Shared checks of the bounds geometry; fills the kernel arguments.
-kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
-                            int64_t nnz, const double* states, const int32_t* rowptr,
-                            const int32_t* cols, const kbl_vgrid* vgrid, int max1d,
-                            kbl::BoundsArgs* a) {
+kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_elem, int64_t n_src,
+                            int32_t n_s, int64_t nnz, const double* states,
+                            const int32_t* rowptr, const int32_t* cols, const kbl_vgrid* vgrid,
+                            int max1d, kbl::BoundsArgs* a) {
     double half_delta = 0.0;
     kbl_status rc = check_params(params, dim, &half_delta);
     if (rc != KBL_OK) return rc;
-    if (n_elem < 0 || n_s < 1 || nnz < 0 || !vgrid) return KBL_ERR_ARG;
+    if (n_elem < 0 || n_src < 0 || n_s < 1 || nnz < 0 || !vgrid) return KBL_ERR_ARG;
     if (n_elem > 0 && (!states || !rowptr)) return KBL_ERR_ARG;
     if (nnz > 0 && !cols) return KBL_ERR_ARG;
-    if (n_elem > INT64_MAX / n_s || nnz > INT64_MAX / (n_s * 8)) return KBL_ERR_ARG;
+    if (n_src > INT64_MAX / n_s || nnz > INT64_MAX / (n_s * 8)) return KBL_ERR_ARG;
     const kbl_vgrid g = *vgrid;
     if (g.mode != KBL_GRID_GLOBAL && g.mode != KBL_GRID_STENCIL) return KBL_ERR_GRID;
     for (int j = 0; j < dim; ++j) {
@@ -63,10 +65,12 @@ kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_ele
     a->rowptr = rowptr;
     a->cols = cols;
     a->n_elem = n_elem;
-    a->n_nodes = n_elem * n_s;
+    a->n_src = n_src;
+    a->n_nodes = n_src * n_s;
     a->nnz = nnz;
     a->n_s = n_s;
     a->grid_mode = g.mode;
+    a->energy_perstate = (params->flags & KBL_FLAG_ENERGY_PERSTATE) ? 1 : 0;
     a->nx = g.n[0];
     a->ny = dim == 2 ? g.n[1] : 1;
     a->lo0 = g.lo[0];
@@ -92,10 +96,12 @@ kbl_status make_limit_args(const kbl_params* params, int32_t dim, int64_t n_elem
     double csum = 0.0;
     for (int j = 0; j < n_s; ++j) {
         const double c = node_weights[j];
-        if (!(c > 0.0) || !isfinite(c)) return KBL_ERR_ARG;
+        if (!(c >= 0.0) || !isfinite(c)) return KBL_ERR_ARG;
         a->c[j] = c;
         csum += c;
     }
+    if (!(csum > 0.0)) return KBL_ERR_ARG;
+    a->independent = (params->flags & KBL_FLAG_INDEPENDENT_ALPHA) ? 1 : 0;
     a->n_elem = n_elem;
     a->n_nodes = n_elem * n_s;
     a->n_s = n_s;
@@ -140,6 +146,46 @@ hipError_t launch_bounds_any(const kbl::BoundsArgs& a, int dim, int prec, int ti
                                  : kbl::launch_bounds_mixed(a, prec, st, tile);
 }
 
+
+// Shared body of kbl_compute_bounds (source units = elements of n_s nodes)
+// and kbl_compute_bounds_nodes (source units = single nodes).
+kbl_status compute_bounds_impl(const kbl_params* params, int32_t dim, int64_t n_elem,
+                               int64_t n_src, int32_t n_s, int64_t nnz, const double* states,
+                               const int32_t* rowptr, const int32_t* cols,
+                               const kbl_vgrid* vgrid, double* bounds, uint32_t* elem_status,
+                               void* stream) {
+    kbl::BoundsArgs a;
+    kbl_status rc = make_bounds_args(params, dim, n_elem, n_src, n_s, nnz, states, rowptr, cols,
+                                     vgrid, kMax1DNodes, &a);
+    if (rc != KBL_OK) return rc;
+    if (n_elem > 0 && !bounds) return KBL_ERR_ARG;
+    const int prec = params->precision;
+    if (prec != KBL_PREC_FP64 && prec != KBL_PREC_MIXED_BF16 && prec != KBL_PREC_MIXED_FP16 &&
+        prec != KBL_PREC_MIXED_FP32)
+        return KBL_ERR_UNSUPPORTED;
+    if (prec != KBL_PREC_FP64 && (dim != 2 || a.energy_perstate)) return KBL_ERR_UNSUPPORTED;
+    a.bounds = bounds;
+    a.status = elem_status;
+    if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
+    if (a.energy_perstate) {
+        const hipError_t err = kbl::launch_bounds_fp64_energy(a, dim, (hipStream_t)stream);
+        return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+    }
+    // launch choice: a tuning-knob override, else an autotuned choice, else the defaults
+    int tile = -1;
+    TuneVal tv;
+    if (tuned(tune_key(a, dim, prec), &tv)) {
+        tile = tv.tile;
+        a.grid_blocks = tv.blocks;
+    }
+    if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE"))
+        tile = atoi(env);
+    if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
+    if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, a.nx, a.ny)) tile = -1;
+    const hipError_t err = launch_bounds_any(a, dim, prec, tile, (hipStream_t)stream);
+    return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
 }  // namespace
 
 extern "C" {
@@ -175,31 +221,17 @@ kbl_status kbl_compute_bounds(const kbl_params* params, int32_t dim, int64_t n_e
                               const int32_t* rowptr, const int32_t* cols,
                               const kbl_vgrid* vgrid, double* bounds,
                               uint32_t* elem_status, void* stream) {
-    kbl::BoundsArgs a;
-    kbl_status rc = make_bounds_args(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid,
-                                     kMax1DNodes, &a);
-    if (rc != KBL_OK) return rc;
-    if (n_elem > 0 && !bounds) return KBL_ERR_ARG;
-    const int prec = params->precision;
-    if (prec != KBL_PREC_FP64 && prec != KBL_PREC_MIXED_BF16 && prec != KBL_PREC_MIXED_FP16 &&
-        prec != KBL_PREC_MIXED_FP32)
-        return KBL_ERR_UNSUPPORTED;
-    if (prec != KBL_PREC_FP64 && dim != 2) return KBL_ERR_UNSUPPORTED;
-    a.bounds = bounds;
-    a.status = elem_status;
-    // launch choice: a tuning-knob override, else an autotuned choice, else the defaults
-    int tile = -1;
-    TuneVal tv;
-    if (tuned(tune_key(a, dim, prec), &tv)) {
-        tile = tv.tile;
-        a.grid_blocks = tv.blocks;
-    }
-    if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE"))
-        tile = atoi(env);
-    if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
-    if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, a.nx, a.ny)) tile = -1;
-    hipError_t err = launch_bounds_any(a, dim, prec, tile, (hipStream_t)stream);
-    return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+    return compute_bounds_impl(params, dim, n_elem, n_elem, n_s, nnz, states, rowptr, cols, vgrid,
+                               bounds, elem_status, stream);
+}
+
+kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64_t n_elem,
+                                    int64_t n_nodes, int64_t nnz, const double* states,
+                                    const int32_t* rowptr, const int32_t* cols,
+                                    const kbl_vgrid* vgrid, double* bounds,
+                                    uint32_t* elem_status, void* stream) {
+    return compute_bounds_impl(params, dim, n_elem, n_nodes, 1, nnz, states, rowptr, cols, vgrid,
+                               bounds, elem_status, stream);
 }
 
 int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
@@ -207,9 +239,10 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
                             const int32_t* cols, const kbl_vgrid* vgrid, double* bounds,
                             uint32_t* elem_status, int64_t sample_elems, void* stream) {
     kbl::BoundsArgs a;
-    if (make_bounds_args(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid, kMax1DNodes,
-                         &a) != KBL_OK)
+    if (make_bounds_args(params, dim, n_elem, n_elem, n_s, nnz, states, rowptr, cols, vgrid,
+                         kMax1DNodes, &a) != KBL_OK)
         return -1;
+    if (a.energy_perstate) return -1;      // one kernel per shape: nothing to choose
     const int prec = params->precision;
     if (prec != KBL_PREC_FP64 && (dim != 2 || prec < KBL_PREC_MIXED_BF16 || prec > KBL_PREC_MIXED_FP32))
         return -1;
@@ -312,8 +345,8 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
                                      double* grad_bounds, uint32_t* elem_status,
                                      void* workspace, size_t workspace_bytes, void* stream) {
     kbl::BoundsArgs fa;
-    kbl_status rc = make_bounds_args(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid,
-                                     kMax1DBackwardNodes, &fa);
+    kbl_status rc = make_bounds_args(params, dim, n_elem, n_elem, n_s, nnz, states, rowptr, cols,
+                                     vgrid, kMax1DBackwardNodes, &fa);
     if (rc != KBL_OK) return rc;
     kbl::LimitArgs la;
     rc = make_limit_args(params, dim, n_elem, n_s, node_weights, &la);
@@ -323,6 +356,7 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
         prec != KBL_PREC_MIXED_FP32)
         return KBL_ERR_UNSUPPORTED;
     if (prec != KBL_PREC_FP64 && dim != 2) return KBL_ERR_UNSUPPORTED;
+    if (params->flags != 0) return KBL_ERR_UNSUPPORTED;   // default method only
     if (n_elem == 0) return KBL_OK;
     if (!solution || !grad_limited || !grad_states || !grad_solution) return KBL_ERR_ARG;
     if (fwd_bounds && !fwd_status) return KBL_ERR_ARG;

@@ -162,7 +162,7 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t 
     double lx = kInf, hx = -kInf, ly = kInf, hy = -kInf, ra = -kInf, rl = -kInf;
     for (int64_t s = tid; s < S; s += NT) {
         const int32_t col = p.cols[row0 + s / p.n_s];
-        if (col < 0 || col >= p.n_elem) { bad |= KBL_ST_BAD_STENCIL; continue; }
+        if (col < 0 || col >= p.n_src) { bad |= KBL_ST_BAD_STENCIL; continue; }
         const Prim st = load_prim<D>(p, (int64_t)col * p.n_s + s % p.n_s);
         if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
         const Coef c = make_coef<D>(p, st);

@@ -197,6 +197,211 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
     }
 }
 
+// ------------------------------------------- energy from per-state integrand
+// Reading of Sec. 3.6 where the energy integrand is taken per state,
+// E_min/max = sum_u M min/max_i g_i(u) (|u|^2/2 + theta_i delta/2), relaxed by
+// (1 -+ r) like the distributions (eq. relaxed); rho and m as before.  The
+// product g_i (h + c_i) has no log-domain shortcut, so the envelopes are kept
+// in value space.  In 2D g_i is still separable in value space,
+// g_i = exp(A_i[x]) exp(B_i[y]): both factors come from LDS tables built per
+// chunk of states, and a pair costs one multiply for g, an add and a multiply
+// for the integrand and four min/max.
+template <int BX, int BY, int TX, int TY>
+__global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
+    constexpr int NT = BX * BY;
+    constexpr int NXM = BX * TX;
+    constexpr int NYM = BY * TY;
+    constexpr int kTabStates = 32;
+    static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    __shared__ Coef sC[kMaxStates];
+    __shared__ double sEA[kTabStates][NXM];
+    __shared__ double sEB[kTabStates][NYM];
+    __shared__ double sCs[kTabStates];        // theta delta / 2 per state
+    __shared__ Red red;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = tid / BX;
+    const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+
+    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+        const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
+        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
+            if (tid == 0) store_nan<2>(p, e, KBL_ST_BAD_STENCIL);
+            continue;
+        }
+        const int64_t S = (row1 - row0) * p.n_s;
+        double box[4];
+        const uint32_t flags = stencil_prologue<2, NT>(p, row0, S, red, sC, box);
+        if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
+            if (tid == 0) store_nan<2>(p, e, flags);
+            continue;
+        }
+        const double lox = box[0], loy = box[2];
+        const double hx = (box[1] - box[0]) / (double)(p.nx - 1);
+        const double hy = (box[3] - box[2]) / (double)(p.ny - 1);
+        double ux[TX], uy[TY], hux[TX], huy[TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+            const int j = tx + BX * i;
+            ux[i] = lox + (j < p.nx ? j : p.nx - 1) * hx;
+            hux[i] = 0.5 * ux[i] * ux[i];
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int jj = ty + BY * j;
+            uy[j] = loy + (jj < p.ny ? jj : p.ny - 1) * hy;
+            huy[j] = 0.5 * uy[j] * uy[j];
+        }
+        double gn[TX][TY], gx[TX][TY], en[TX][TY], ex[TX][TY];
+#pragma unroll
+        for (int i = 0; i < TX; ++i)
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                gn[i][j] = kInf; gx[i][j] = -kInf; en[i][j] = kInf; ex[i][j] = -kInf;
+            }
+
+        for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
+            const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
+            if (c0 > 0) stage_chunk<2, NT>(p, row0, c0, cn, sC);
+            for (int t0 = 0; t0 < cn; t0 += kTabStates) {
+                const int tn = (cn - t0) < kTabStates ? (cn - t0) : kTabStates;
+                __syncthreads();
+                for (int idx = tid; idx < tn * NXM; idx += NT) {
+                    const int s = idx / NXM, i = idx - s * NXM;
+                    const int ic = i < p.nx ? i : p.nx - 1;
+                    const Coef& c = sC[t0 + s];
+                    const double d = (lox + ic * hx) - c.ux;
+                    sEA[s][i] = exp(fma(c.nk * d, d, c.a));
+                }
+                for (int idx = tid; idx < tn * NYM; idx += NT) {
+                    const int s = idx / NYM, j = idx - s * NYM;
+                    const int jc = j < p.ny ? j : p.ny - 1;
+                    const Coef& c = sC[t0 + s];
+                    const double d = (loy + jc * hy) - c.uy;
+                    sEB[s][j] = exp((c.nk * d) * d);
+                }
+                for (int s = tid; s < tn; s += NT) sCs[s] = p.half_delta * (-0.5 / sC[t0 + s].nk);
+                __syncthreads();
+#pragma unroll 2
+                for (int s = 0; s < tn; ++s) {
+                    const double cs = sCs[s];
+                    double ea[TX], hc[TX], eb[TY];
+#pragma unroll
+                    for (int i = 0; i < TX; ++i) {
+                        ea[i] = sEA[s][tx + BX * i];
+                        hc[i] = hux[i] + cs;
+                    }
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) eb[j] = sEB[s][ty + BY * j];
+#pragma unroll
+                    for (int i = 0; i < TX; ++i)
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            const double g = ea[i] * eb[j];
+                            const double eg = g * (hc[i] + huy[j]);
+                            gn[i][j] = fmin(gn[i][j], g);
+                            gx[i][j] = fmax(gx[i][j], g);
+                            en[i][j] = fmin(en[i][j], eg);
+                            ex[i][j] = fmax(ex[i][j], eg);
+                        }
+                }
+            }
+        }
+
+        double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < TX; ++i) {
+            const int jx = tx + BX * i;
+            if (jx >= p.nx) continue;
+            const double wx = hx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const int jy = ty + BY * j;
+                if (jy >= p.ny) continue;
+                const double M = wx * (hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
+                const double ftn = rm * gn[i][j], ftx = rp * gx[i][j];
+                part[0] += M * ftn;
+                part[1] += M * ftx;
+                part[2] += M * (rm * en[i][j]);
+                part[3] += M * (rp * ex[i][j]);
+                if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
+                else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
+                if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
+                else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
+            }
+        }
+        block_sum<NT, 8>(part, red);
+        if (tid == 0) store_bounds<2>(p, e, part, flags);
+    }
+}
+
+// 1D: no separability; one exp per (state, node) pair.
+template <int NT, int T>
+__global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
+    __shared__ Coef sC[kMaxStates];
+    __shared__ Red red;
+    const int tid = threadIdx.x;
+    const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+        const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
+        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
+            if (tid == 0) store_nan<1>(p, e, KBL_ST_BAD_STENCIL);
+            continue;
+        }
+        const int64_t S = (row1 - row0) * p.n_s;
+        double box[4];
+        const uint32_t flags = stencil_prologue<1, NT>(p, row0, S, red, sC, box);
+        if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
+            if (tid == 0) store_nan<1>(p, e, flags);
+            continue;
+        }
+        const double lo = box[0];
+        const double h = (box[1] - box[0]) / (double)(p.nx - 1);
+        double u[T], hu[T], gn[T], gx[T], en[T], ex[T];
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const int j = tid + NT * i;
+            u[i] = lo + (j < p.nx ? j : p.nx - 1) * h;
+            hu[i] = 0.5 * u[i] * u[i];
+            gn[i] = kInf; gx[i] = -kInf; en[i] = kInf; ex[i] = -kInf;
+        }
+        for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
+            const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
+            if (c0 > 0) stage_chunk<1, NT>(p, row0, c0, cn, sC);
+            for (int s = 0; s < cn; ++s) {
+                const Coef c = sC[s];
+                const double cs = p.half_delta * (-0.5 / c.nk);
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const double d = u[i] - c.ux;
+                    const double g = exp(fma(c.nk * d, d, c.a));
+                    const double eg = g * (hu[i] + cs);
+                    gn[i] = fmin(gn[i], g);
+                    gx[i] = fmax(gx[i], g);
+                    en[i] = fmin(en[i], eg);
+                    ex[i] = fmax(ex[i], eg);
+                }
+            }
+        }
+        double part[6] = {0, 0, 0, 0, 0, 0};
+#pragma unroll
+        for (int i = 0; i < T; ++i) {
+            const int j = tid + NT * i;
+            if (j >= p.nx) continue;
+            const double M = h * ((j == 0 || j == p.nx - 1) ? 0.5 : 1.0);
+            const double ftn = rm * gn[i], ftx = rp * gx[i];
+            part[0] += M * ftn;
+            part[1] += M * ftx;
+            part[2] += M * (rm * en[i]);
+            part[3] += M * (rp * ex[i]);
+            if (u[i] < 0.0) { part[4] += M * u[i] * ftx; part[5] += M * u[i] * ftn; }
+            else            { part[4] += M * u[i] * ftn; part[5] += M * u[i] * ftx; }
+        }
+        block_sum<NT, 6>(part, red);
+        if (tid == 0) store_bounds<1>(p, e, part, flags);
+    }
+}
+
 // ---------------------------------------------------------------- 1D kernel
 // No separability to exploit: each pair costs sub, mul and two fma before the
 // four min/max.  Coefficients are broadcast from LDS.
@@ -326,6 +531,25 @@ bool bounds_tile_fits_2d(int tile, int nx, int ny) {
     if (tile < 0 || tile >= kNumTiles2D) return false;
     const Tile2D& t = kTiles2D[tile];
     return nx <= t.bx * t.tx && ny <= t.by * t.ty;
+}
+
+hipError_t launch_bounds_fp64_energy(const BoundsArgs& a, int dim, hipStream_t stream) {
+    if (a.n_elem == 0) return hipSuccess;
+    if (dim == 2) {
+        const int n = a.nx > a.ny ? a.nx : a.ny;
+        if (n <= 16) return launch(bounds_fp64_2d_energy<16, 16, 1, 1>, 256, a, stream);
+        if (n <= 32) return launch(bounds_fp64_2d_energy<16, 16, 2, 2>, 256, a, stream);
+        if (n <= 48) return launch(bounds_fp64_2d_energy<16, 16, 3, 3>, 256, a, stream);
+        if (n <= 64) return launch(bounds_fp64_2d_energy<16, 16, 4, 4>, 256, a, stream);
+        return hipErrorInvalidValue;
+    }
+    if (a.nx <= 64) return launch(bounds_fp64_1d_energy<64, 1>, 64, a, stream);
+    if (a.nx <= 256) return launch(bounds_fp64_1d_energy<256, 1>, kThreads, a, stream);
+    if (a.nx <= 512) return launch(bounds_fp64_1d_energy<256, 2>, kThreads, a, stream);
+    if (a.nx <= 1024) return launch(bounds_fp64_1d_energy<256, 4>, kThreads, a, stream);
+    if (a.nx <= 2048) return launch(bounds_fp64_1d_energy<256, 8>, kThreads, a, stream);
+    if (a.nx <= 4096) return launch(bounds_fp64_1d_energy<256, 16>, kThreads, a, stream);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile) {

@@ -19,10 +19,12 @@ struct BoundsArgs {
     double* bounds;
     uint32_t* status;
     int64_t n_elem;
-    int64_t n_nodes;
+    int64_t n_src;      // source units the stencil columns index (elements, or nodes)
+    int64_t n_nodes;    // columns of `states` = n_src * n_s
     int64_t nnz;
-    int32_t n_s;
+    int32_t n_s;        // nodes per source unit (1 for node-level stencils)
     int32_t grid_mode;
+    int32_t energy_perstate;
     int32_t nx, ny;
     double lo0, lo1, hi0, hi1, k;
     double gm1;         // gamma - 1
@@ -55,13 +57,16 @@ struct LimitArgs {
     double p_floor;
     double eps;
     double inv_csum;                 // 1 / sum_j c_j
-    double c[kMaxLimitNodes];        // element quadrature weights
+    int32_t independent;             // per-component alpha instead of the coupled minimum
+    double c[kMaxLimitNodes];        // element mean weights (>= 0, positive sum)
 };
 
 // Host-side launchers (one per translation unit).  They return hipSuccess or
 // the launch error; argument checking happened before.
 // tile < 0 selects the default 2D tile for the grid size.
 hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile);
+// Energy bounds from the per-state integrand (KBL_FLAG_ENERGY_PERSTATE).
+hipError_t launch_bounds_fp64_energy(const BoundsArgs& a, int dim, hipStream_t stream);
 int bounds_tile_count_2d();
 bool bounds_tile_fits_2d(int tile, int nx, int ny);
 int mixed_tile_count();

@@ -9,7 +9,8 @@
 // the SoA rows, so loads and stores are coalesced.
 //  - mean with positive weights c_j (Assumption (iii)(a) of Sec. 4);
 //  - alpha_i per component (eq. alpha) with the epsilon rule, coupled by the
-//    minimum (eq. limiter);
+//    minimum (eq. limiter), or each component with its own alpha_i (the
+//    independent option of the same section);
 //  - P_min over the limited nodes (eq. pmin) and, below the floor, the second
 //    blend with alpha_P (eq. doublelimit).  An undefined pressure counts as
 //    below the floor.  P(mean) <= floor gives alpha_P = 0 (flattened element).
@@ -74,7 +75,7 @@ __global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
     }
 
     uint32_t st = 0;
-    double wbar[NV];
+    double wbar[NV], acomp[NV];
     double amin = 1.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
@@ -94,13 +95,15 @@ __global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
             if (ru < av) av = ru;
             if (rl < av) av = rl;
         }
+        acomp[v] = av;
         if (av < amin) amin = av;
     }
     if (amin < 1.0) st |= KBL_ST_LIMITED;
 
+    // coupled (eq. limiter) or independent per-component blend
     double wt[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + amin * (w[v] - wbar[v]);
+    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + (p.independent ? acomp[v] : amin) * (w[v] - wbar[v]);
 
     double P = live ? pressure<D>(p.gm1, wt) : kInf;
     if (isnan(P)) P = -kInf;

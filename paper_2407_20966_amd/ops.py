@@ -17,7 +17,8 @@ from . import _lib as L
 
 def make_params(gamma: float, r_fac: float = 1e-3, rho_floor: float = 1e-12,
                 p_floor: float = 1e-12, eps_alpha: float = 1e-13,
-                precision: int = L.PREC_FP64) -> L.Params:
+                precision: int = L.PREC_FP64, independent_alpha: bool = False,
+                energy_perstate: bool = False) -> L.Params:
     p = L.Params()
     L.lib().kbl_default_params(C.byref(p), float(gamma))
     p.r_fac = float(r_fac)
@@ -25,6 +26,8 @@ def make_params(gamma: float, r_fac: float = 1e-3, rho_floor: float = 1e-12,
     p.p_floor = float(p_floor)
     p.eps_alpha = float(eps_alpha)
     p.precision = int(precision)
+    p.flags = ((L.FLAG_INDEPENDENT_ALPHA if independent_alpha else 0)
+               | (L.FLAG_ENERGY_PERSTATE if energy_perstate else 0))
     return p
 
 
@@ -95,6 +98,36 @@ def compute_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tenso
                                     _ptr(out), _ptr(status), _stream(dev, stream))
     if rc != L.KBL_OK:
         raise L.KblError(rc, "kbl_compute_bounds")
+    return out, status
+
+
+def compute_bounds_nodes(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor,
+                         vgrid: L.VGrid, params: L.Params, out: Optional[torch.Tensor] = None,
+                         status: Optional[torch.Tensor] = None,
+                         stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Bounds for node-level stencils: row e of the CSR lists node ids (columns of
+    `states`), e.g. an element's solution and flux points plus its neighbours'
+    flux points on the shared faces."""
+    _check(states, "states", torch.float64)
+    dev = states.device
+    _check(rowptr, "rowptr", torch.int32, dev)
+    _check(cols, "cols", torch.int32, dev)
+    dim = states.shape[0] - 2
+    n_elem = rowptr.numel() - 1
+    if out is None:
+        out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
+    else:
+        _check(out, "out", torch.float64, dev)
+        if tuple(out.shape) != (2 * (dim + 2), n_elem):
+            raise ValueError("out has the wrong shape")
+    if status is None:
+        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    rc = L.lib().kbl_compute_bounds_nodes(C.byref(params), dim, n_elem, states.shape[1],
+                                          cols.numel(), _ptr(states), _ptr(rowptr), _ptr(cols),
+                                          C.byref(vgrid), _ptr(out), _ptr(status),
+                                          _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_compute_bounds_nodes")
     return out, status
 
 

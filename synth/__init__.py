@@ -13,6 +13,8 @@ from .workloads import (  # noqa: F401
     make_line_workload,
     make_quad_workload,
     make_tri_workload,
+    make_quad_fr_workload,
+    NodeWorkload,
     sample_elements,
     WORKLOADS,
 )

@@ -330,6 +330,177 @@ def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int 
                      "N": N})
 
 
+# ----------------------------------------------------------------------------
+# 2D quads with the node-level stencil of an FR scheme: solution points plus
+# flux points on the faces (the stencil the paper runs, Sec. 5).
+# ----------------------------------------------------------------------------
+
+@dataclass
+class NodeWorkload:
+    """Inputs of the node-level path.
+
+    states  [dim+2, n_state_nodes]: every node a stencil may list; the first
+            n_elem*n_sol are solution points (element-major), then n_elem*n_flux
+            flux points (element-major, face-major: faces x-, x+, y-, y+).
+    rowptr, cols: per element, the node ids of its stencil.
+    target  [dim+2, n_elem*n_v]: the values to limit on V (per element: the
+            n_sol solution points, then its n_flux own flux points).
+    v_weights [n_v]: mean weights on V (Gauss-Legendre on solution points,
+            zero on flux points).
+    """
+
+    name: str
+    dim: int
+    gamma: float
+    n_elem: int
+    n_sol: int
+    n_flux: int
+    states: np.ndarray
+    rowptr: np.ndarray
+    cols: np.ndarray
+    target: np.ndarray
+    v_weights: np.ndarray
+    grid: GridSpec
+    r_fac: float = 1e-3
+    seed: int = BASE_SEED
+    meta: Dict = field(default_factory=dict)
+
+    @property
+    def n_v(self) -> int:
+        return self.n_sol + self.n_flux
+
+    @property
+    def n_state_nodes(self) -> int:
+        return self.states.shape[1]
+
+    def n_vel(self) -> int:
+        return int(np.prod(self.grid.n[: self.dim]))
+
+    def pairs(self) -> int:
+        return int(self.rowptr[-1]) * self.n_vel()
+
+
+def _lagrange_at(xi: np.ndarray, x: float) -> np.ndarray:
+    """Values at x of the Lagrange basis on the nodes xi."""
+    out = np.ones(xi.size)
+    for i in range(xi.size):
+        for k in range(xi.size):
+            if k != i:
+                out[i] *= (x - xi[k]) / (xi[i] - xi[k])
+    return out
+
+
+def _admissible(gamma: float, w: np.ndarray) -> np.ndarray:
+    """rho > 0 and p > 0 per column of conserved states (input screening only)."""
+    rho = w[0]
+    ke = 0.5 * (w[1] ** 2 + w[2] ** 2) / np.where(rho > 0, rho, 1.0)
+    return (rho > 0) & ((gamma - 1.0) * (w[3] - ke) > 0) & np.isfinite(w).all(0)
+
+
+def make_quad_fr_workload(N: int = 64, p: int = 3, seed: int = BASE_SEED + 5,
+                          grid_nodes: int = 48, k: float = 4.0, gamma: float = 1.4,
+                          r_fac: float = 1e-3, name: str = "quad_fr") -> NodeWorkload:
+    """Periodic quads, p = 3: per element the 16 Gauss-Legendre solution points,
+    its 16 flux points (4 per face, at the Gauss-Legendre abscissae along the
+    face) and the 16 flux points of its 4 face neighbours on the shared faces:
+    48 stencil states; V = the 16 solution + 16 own flux points.
+
+    Flux-point states are the element polynomial (Lagrange interpolant of the
+    solution points) evaluated on the face; an element whose face values come
+    out inadmissible (rho <= 0 or p <= 0, at jumps) takes the sampled field
+    values at its face points instead.  The field is the four-quadrant Riemann
+    field of make_quad_workload; the limiter target is W + Delta (zero mean on
+    the solution points) extended to the flux points by the same interpolant.
+    """
+    rng = _rng(seed)
+    n1 = p + 1
+    n_s = n1 * n1
+    xi, wq = np.polynomial.legendre.leggauss(n1)
+    ex = np.arange(N)
+    n_elem = N * N
+    ey_e, ex_e = np.divmod(np.arange(n_elem), N)
+    # solution points (node j = jy*n1 + jx)
+    Xs = ((ex_e[:, None] + 0.5 * (xi[None, :] + 1.0)) / N)[:, None, :].repeat(n1, 1).reshape(n_elem, n_s)
+    Ys = ((ey_e[:, None] + 0.5 * (xi[None, :] + 1.0)) / N)[:, :, None].repeat(n1, 2).reshape(n_elem, n_s)
+    # flux points: faces x- (x = left edge), x+, y-, y+; n1 points each
+    t = 0.5 * (xi + 1.0)
+    Xf = np.stack([np.repeat(ex_e[:, None] / N, n1, 1), np.repeat((ex_e[:, None] + 1) / N, n1, 1),
+                   (ex_e[:, None] + t[None]) / N, (ex_e[:, None] + t[None]) / N], 1)
+    Yf = np.stack([(ey_e[:, None] + t[None]) / N, (ey_e[:, None] + t[None]) / N,
+                   np.repeat(ey_e[:, None] / N, n1, 1), np.repeat((ey_e[:, None] + 1) / N, n1, 1)], 1)
+    Xf = Xf.reshape(n_elem, 4 * n1)
+    Yf = Yf.reshape(n_elem, 4 * n1)
+
+    # four-quadrant Riemann field, sampled anywhere
+    off = rng.uniform(0.2, 0.8, 2)
+    xs, ys = (N // 2 + off[0]) / N, (N // 2 + off[1]) / N
+    rho_q = np.exp(rng.uniform(np.log(0.1), np.log(10.0), 4))
+    p_q = np.exp(rng.uniform(np.log(0.1), np.log(100.0), 4))
+    r_q = rng.uniform(0.0, 3.0, 4)
+    a_q = rng.uniform(0.0, 2 * np.pi, 4)
+    modes = [(rng.uniform(0.5, 1.0, 8), rng.integers(-4, 5, 8), rng.integers(-4, 5, 8),
+              rng.uniform(0.0, 2 * np.pi, 8)) for _ in range(4)]
+
+    def smooth(m, X, Y):
+        amps, kx, ky, ph = m
+        out = np.zeros_like(X)
+        for a, i, j, f in zip(amps, kx, ky, ph):
+            out += a * np.sin(2 * np.pi * (i * X + j * Y) + f)
+        return out / amps.sum()
+
+    def field(X, Y):
+        q = (X >= xs).astype(np.int64) + 2 * (Y >= ys).astype(np.int64)
+        rho = rho_q[q] * (1.0 + 0.01 * smooth(modes[0], X, Y))
+        pr = p_q[q] * (1.0 + 0.01 * smooth(modes[1], X, Y))
+        ux = (r_q * np.cos(a_q))[q] + 0.03 * smooth(modes[2], X, Y)
+        uy = (r_q * np.sin(a_q))[q] + 0.03 * smooth(modes[3], X, Y)
+        return _to_conserved(gamma, rho, [ux, uy], pr)
+
+    W = field(Xs.ravel(), Ys.ravel()).reshape(4, n_elem, n1, n1)    # [v, e, jy, jx]
+    Lm, Lp = _lagrange_at(xi, -1.0), _lagrange_at(xi, 1.0)
+
+    def faces(Wn):                                           # [v, e, jy, jx] -> [v, e, 4*n1]
+        return np.concatenate([np.einsum("veyx,x->vey", Wn, Lm), np.einsum("veyx,x->vey", Wn, Lp),
+                               np.einsum("veyx,y->vex", Wn, Lm), np.einsum("veyx,y->vex", Wn, Lp)],
+                              axis=2)
+
+    F = faces(W)
+    ok = _admissible(gamma, F.reshape(4, -1)).reshape(n_elem, 4 * n1).all(1)
+    if (~ok).any():
+        F[:, ~ok] = field(Xf[~ok].ravel(), Yf[~ok].ravel()).reshape(4, int((~ok).sum()), 4 * n1)
+    sol = W.reshape(4, n_elem * n_s)
+    states = np.concatenate([sol, F.reshape(4, n_elem * 4 * n1)], axis=1)
+
+    # stencil: own solution points, own flux points, neighbours' flux points on the shared faces
+    base = n_elem * n_s
+    fl = lambda e, f: base + e[:, None] * (4 * n1) + f * n1 + np.arange(n1)[None, :]
+    left = ey_e * N + (ex_e - 1) % N
+    right = ey_e * N + (ex_e + 1) % N
+    down = ((ey_e - 1) % N) * N + ex_e
+    up = ((ey_e + 1) % N) * N + ex_e
+    own = np.arange(n_elem)
+    cols = np.concatenate([own[:, None] * n_s + np.arange(n_s)[None, :],
+                           fl(own, 0), fl(own, 1), fl(own, 2), fl(own, 3),
+                           fl(left, 1), fl(right, 0), fl(down, 3), fl(up, 2)], axis=1)
+    per = cols.shape[1]
+    cols = cols.ravel().astype(np.int32)
+    rowptr = np.arange(0, per * n_elem + 1, per).astype(np.int32)
+
+    # limiter target on V
+    w2 = (wq[:, None] * wq[None, :]).ravel()
+    el_cols = np.stack([own, left, right, down, up], 1).ravel().astype(np.int32)
+    el_rowptr = np.arange(0, 5 * n_elem + 1, 5).astype(np.int32)
+    tsol, jumpy = _limit_target(rng, sol, el_rowptr, el_cols, n_s, w2)
+    T = tsol.reshape(4, n_elem, n1, n1)
+    target = np.concatenate([T.reshape(4, n_elem, n_s), faces(T)], axis=2).reshape(4, -1)
+    v_weights = np.concatenate([w2, np.zeros(4 * n1)])
+    grid = GridSpec(GRID_STENCIL, (grid_nodes, grid_nodes), (0.0, 0.0), (0.0, 0.0), k)
+    return NodeWorkload(name, 2, gamma, n_elem, n_s, 4 * n1, np.ascontiguousarray(states),
+                        rowptr, cols, np.ascontiguousarray(target), v_weights, grid, r_fac, seed,
+                        {"jump_elems": np.nonzero(jumpy)[0], "face_fallback": int((~ok).sum()),
+                         "N": N})
+
+
 def make_workload(name: str, **kw) -> Workload:
     return WORKLOADS[name](**kw)
 
@@ -365,4 +536,8 @@ WORKLOADS: Dict[str, Callable[..., Workload]] = {
     # 512^2 quads, p=3, 48x48 per-stencil grid, used for the backward
     "quad512": lambda **kw: make_quad_workload(**{"N": 512, "seed": BASE_SEED + 4,
                                                   "grid_nodes": 48, "name": "quad512", **kw}),
+    # 256^2 quads, p=3, node-level stencils of solution + flux points (48 states)
+    "quad256_fr": lambda **kw: make_quad_fr_workload(**{"N": 256, "seed": BASE_SEED + 5,
+                                                        "grid_nodes": 48, "name": "quad256_fr",
+                                                        **kw}),
 }

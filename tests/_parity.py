@@ -25,6 +25,12 @@ def stencil_momentum_scale(wl, elems=None):
     return full if elems is None else full[elems]
 
 
+def node_stencil_momentum_scale(states, rowptr, cols, dim, elems):
+    """Node-level stencils: max over the listed nodes of |m|_1 + sqrt(rho*E)."""
+    node_scale = np.abs(states[1:1 + dim]).sum(0) + np.sqrt(np.abs(states[0] * states[dim + 1]))
+    return np.array([node_scale[cols[rowptr[e]:rowptr[e + 1]]].max() for e in elems])
+
+
 def element_value_scale(wl, arr, elems=None):
     """Per (variable, element): max |arr| over the element's nodes, momentum rows
     floored by sqrt(rho E) of the element."""

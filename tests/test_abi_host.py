@@ -30,7 +30,7 @@ def test_header_declares_expected_entry_points():
     syms = L.header_symbols()
     for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
               "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes",
-              "kbl_autotune_bounds", "kbl_autotune_clear"):
+              "kbl_autotune_bounds", "kbl_autotune_clear", "kbl_compute_bounds_nodes"):
         assert s in syms
 
 
@@ -62,7 +62,7 @@ def test_defaults_and_strings(lib):
     p = L.Params()
     lib.kbl_default_params(C.byref(p), 1.4)
     assert (p.gamma, p.r_fac, p.rho_floor, p.p_floor, p.eps_alpha) == (1.4, 1e-3, 1e-12, 1e-12, 1e-13)
-    assert p.precision == L.PREC_FP64 and p.reserved == 0
+    assert p.precision == L.PREC_FP64 and p.flags == 0
     for code in range(7):
         assert lib.kbl_status_string(code)
     assert lib.kbl_version() >= 100
@@ -111,7 +111,8 @@ def test_bounds_rejects_bad_sizes(lib, case, expect):
     (dict(r_fac=-1e-3), L.KBL_ERR_ARG),
     (dict(rho_floor=-1.0), L.KBL_ERR_ARG),
     (dict(eps_alpha=float("nan")), L.KBL_ERR_ARG),
-    (dict(reserved=1), L.KBL_ERR_ARG),
+    (dict(flags=0x100), L.KBL_ERR_ARG),
+    (dict(flags=L.FLAG_ENERGY_PERSTATE, precision=L.PREC_MIXED_FP32), L.KBL_ERR_UNSUPPORTED),
     (dict(precision=7), L.KBL_ERR_UNSUPPORTED),
 ])
 def test_bounds_rejects_bad_params(lib, pkw, expect):
@@ -152,7 +153,6 @@ def _limit(lib, p, w, dim=2, n_elem=4, n_s=None):
 
 def test_limit_rejects_bad_weights(lib):
     p = _params(lib)
-    assert _limit(lib, p, [1.0, 0.0, 1.0]) == L.KBL_ERR_ARG
     assert _limit(lib, p, [1.0, -1.0, 1.0]) == L.KBL_ERR_ARG
     assert _limit(lib, p, [1.0, float("nan")]) == L.KBL_ERR_ARG
     assert _limit(lib, p, [1.0] * 65) == L.KBL_ERR_ARG      # n_s > 64
@@ -193,7 +193,7 @@ def test_backward_rejects_bad_arguments(lib):
     assert _backward(lib, _params(lib, gamma=1.0), g) == L.KBL_ERR_GAMMA
     assert _backward(lib, _params(lib), _grid(n=(65, 48))) == L.KBL_ERR_GRID
     assert _backward(lib, _params(lib), _grid(n=(2049, 2)), dim=1, n_s=4) == L.KBL_ERR_GRID
-    assert _backward(lib, _params(lib), g, weights=[1.0] * 15 + [0.0]) == L.KBL_ERR_ARG
+    assert _backward(lib, _params(lib), g, weights=[0.0] * 16) == L.KBL_ERR_ARG   # zero sum
 
 
 def _autotune(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20):
@@ -209,3 +209,35 @@ def test_autotune_rejects_bad_arguments(lib):
     assert _autotune(lib, _params(lib, precision=L.PREC_MIXED_FP16), _grid(n=(64, 2)), dim=1) == -1
     assert _autotune(lib, _params(lib), g, n_elem=0) == -1
     lib.kbl_autotune_clear()
+
+
+def _bounds_nodes(lib, p, g, n_elem=4, n_nodes=64, nnz=20, ptrs=True):
+    P = FAKE if ptrs else None
+    return lib.kbl_compute_bounds_nodes(C.byref(p), 2, n_elem, n_nodes, nnz, P, P, P, C.byref(g),
+                                        P, None, None)
+
+
+def test_node_stencil_rejects_bad_arguments(lib):
+    g = _grid()
+    assert _bounds_nodes(lib, _params(lib), g, n_nodes=-1) == L.KBL_ERR_ARG
+    assert _bounds_nodes(lib, _params(lib), g, ptrs=False) == L.KBL_ERR_ARG
+    assert _bounds_nodes(lib, _params(lib, 1.0), g) == L.KBL_ERR_GAMMA
+    assert _bounds_nodes(lib, _params(lib), _grid(n=(65, 48))) == L.KBL_ERR_GRID
+
+
+def test_limit_weights_may_be_zero_but_not_all():
+    p = _params(lib=L.lib())
+    lib = L.lib()
+    assert _limit(lib, p, [0.0, 0.0, 0.0]) == L.KBL_ERR_ARG
+    # zero weights on some nodes are accepted: the call then fails only on the
+    # (fake) device pointers, which it never reaches without a GPU, so check
+    # the argument validation through an empty element count instead
+    w = np.array([1.0, 0.0, 2.0])
+    assert lib.kbl_limit(C.byref(p), 2, 0, 3, None, None, w.ctypes.data_as(C.c_void_p),
+                         None, None, None, None) == L.KBL_OK
+
+
+def test_backward_default_method_only(lib):
+    g = _grid()
+    for flags in (L.FLAG_INDEPENDENT_ALPHA, L.FLAG_ENERGY_PERSTATE):
+        assert _backward(lib, _params(lib, flags=flags), g) == L.KBL_ERR_UNSUPPORTED
