@@ -50,6 +50,43 @@ WORKLOAD_TEXT = {
 }
 
 
+KERNEL_SOURCES = ("paper_2407_20966_amd/csrc/bounds_fp64.hip",
+                  "paper_2407_20966_amd/csrc/bounds_common.h",
+                  "paper_2407_20966_amd/csrc/kbl_internal.h")
+TRAFFIC_FILE = "profiles/bounds_fp64_2d_quad256_traffic.txt"
+
+
+def kernel_sources_sha() -> str:
+    """sha256 of the FP64 bounds kernel's sources (identifies what was profiled)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def profiled_traffic(kernel: str, grid_threads: int, workload: str):
+    """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
+    summary is for another kernel, launch shape or workload, or the kernel's
+    sources changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        same = (kv["kernel"] == kernel and int(kv["grid_threads"]) == grid_threads
+                and kv["workload"] == workload and kv["source_sha256"] == kernel_sources_sha())
+        return float(kv["bytes_per_launch"]) if same else None
+    except (KeyError, ValueError):
+        return None
+
+
 def pair_ops(dim: int) -> int:
     """Algorithmic VALU lane-ops per (stencil state, velocity node) pair.
 
@@ -82,6 +119,105 @@ def cpu_baseline(wl, target_s: float = 12.0):
                       f"{dt:.1f} s wall, FP64 direct-form oracle (gcc -O2, OpenMP)"}
 
 
+
+def _time_events(torch, stream, fn, steps, warmup):
+    """Average ms of fn() over `steps` calls, HIP events on the launch stream."""
+    for _ in range(max(1, warmup)):
+        fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream, ms_step, b_ms):
+    """The method's variants on the same inputs (and the node-level stencil on
+    its own workload): per-state energy integrand, strict bounds (r = 0),
+    independent limiting, solution + flux point stencils."""
+    dev = st.device
+    steps = max(2, args.steps // 2)
+    out = {}
+    bnd = torch.empty((8, wl.n_elem), dtype=torch.float64, device=dev)
+    bst = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+    lim = torch.empty_like(tg)
+    # energy bounds from the per-state integrand: 7 ops per pair (g = EA EB,
+    # h + c, product, four min/max) in value space
+    prm_e = kbl.make_params(wl.gamma, r_fac=wl.r_fac, energy_perstate=True)
+    ms = _time_events(torch, stream, lambda: kbl.compute_bounds(
+        st, rp, cl, wl.n_s, vg, prm_e, out=bnd, status=bst, stream=stream), steps, args.warmup)
+    ops = wl.pairs() * 7
+    out["energy_perstate"] = {"bounds_ms": ms, "vs_default_bounds": ms / b_ms,
+                              "ops_per_pair": 7, "frac": ops / (ms * 1e-3) / VALU_PEAK_OPS}
+    # strict bounds: same kernels, r_fac = 0; report how many more elements limit
+    prm0 = kbl.make_params(wl.gamma, r_fac=0.0)
+    prm1 = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    al = torch.empty((2, wl.n_elem), dtype=torch.float64, device=dev)
+
+    def step0():
+        kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm0, out=bnd, status=bst, stream=stream)
+        kbl.limit(tg, bnd, wl.node_weights, wl.n_s, prm0, out=lim, alpha=al, stream=stream)
+    ms0 = _time_events(torch, stream, step0, steps, args.warmup)
+    lim0 = int((al[0] < 1).sum())
+    kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm1, out=bnd, status=bst, stream=stream)
+    kbl.limit(tg, bnd, wl.node_weights, wl.n_s, prm1, out=lim, alpha=al, stream=stream)
+    torch.cuda.synchronize()
+    lim1 = int((al[0] < 1).sum())
+    out["strict_r0"] = {"ms_per_step": ms0, "value": wl.n_elem / (ms0 * 1e-3),
+                        "limited_elements": lim0, "limited_elements_relaxed": lim1}
+    # independent limiting (limiter only; bounds from the default method)
+    prm_i = kbl.make_params(wl.gamma, r_fac=wl.r_fac, independent_alpha=True)
+    msi = _time_events(torch, stream, lambda: kbl.limit(
+        tg, bnd, wl.node_weights, wl.n_s, prm_i, out=lim, stream=stream), steps, args.warmup)
+    out["independent_alpha"] = {"limit_ms": msi,
+                                "limit_hbm_frac": (2 * tg.numel() * 8 + bnd.numel() * 8)
+                                / (msi * 1e-3) / HBM_PEAK}
+    # node-level stencils of solution + flux points (256^2 quads, 48 states each)
+    if not args.no_fr:
+        print("[bench] generating quad256_fr", file=sys.stderr, flush=True)
+        fr = synth.make_workload("quad256_fr")
+        fst = torch.from_numpy(fr.states).to(dev)
+        frp = torch.from_numpy(fr.rowptr).to(dev)
+        fcl = torch.from_numpy(fr.cols).to(dev)
+        ftg = torch.from_numpy(fr.target).to(dev)
+        fg = fr.grid
+        fvg = kbl.make_vgrid(fg.mode, fg.n[:2], fg.lo, fg.hi, fg.k)
+        fb = torch.empty((8, fr.n_elem), dtype=torch.float64, device=dev)
+        fs = torch.empty(fr.n_elem, dtype=torch.int32, device=dev)
+        flim = torch.empty_like(ftg)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+
+        def fstep(rec=False):
+            if rec:
+                ev[0].record(stream)
+            kbl.compute_bounds_nodes(fst, frp, fcl, fvg, prm1, out=fb, status=fs, stream=stream)
+            if rec:
+                ev[1].record(stream)
+            kbl.limit(ftg, fb, fr.v_weights, fr.n_v, prm1, out=flim, stream=stream)
+            if rec:
+                ev[2].record(stream)
+        msf = _time_events(torch, stream, fstep, steps, args.warmup)
+        fstep(rec=True)
+        torch.cuda.synchronize()
+        fbms = ev[0].elapsed_time(ev[1])
+        out["node_stencil_fr"] = {
+            "workload": "quad256_fr: 256x256 periodic quads, p=3, per element 16 solution "
+                        "points + 16 own flux points + 16 neighbour flux points (48 states), "
+                        "48x48 per-stencil grid, V = 32 nodes (flux points weight 0)",
+            "ms_per_step": msf, "value": fr.n_elem / (msf * 1e-3), "unit": "elements/s",
+            "bounds_ms": fbms, "frac": fr.pairs() * 6 / (fbms * 1e-3) / VALU_PEAK_OPS}
+        print(f"[bench] node-stencil FR: {msf:.3f} ms/step (bounds {fbms:.3f} ms)",
+              file=sys.stderr, flush=True)
+        del fst, ftg, flim
+    print(f"[bench] variants: energy {ms:.3f} ms, strict {ms0:.3f} ms/step, independent limit "
+          f"{msi:.3f} ms", file=sys.stderr, flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -91,6 +227,10 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
+    ap.add_argument("--no-fr", action="store_true", help="skip the node-level stencil timing")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the variant timings (energy reading, r = 0, independent "
+                         "limiting, node-level stencils)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default launch configuration instead of an autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -174,9 +314,19 @@ def main(argv=None):
     pairs = wl.pairs()
     ops = pairs * pair_ops(wl.dim)
     achieved = ops / (b_ms * 1e-3)
+    kname, grid_threads = "bounds_fp64_2d" if wl.dim == 2 else "bounds_fp64_1d", None
+    if wl.dim == 2 and "fp64" in tuned:
+        bx, by, tx, ty, md = kbl._lib.FP64_TILES[tuned["fp64"]["tile"]]
+        kname = f"bounds_fp64_2d<{bx}, {by}, {tx}, {ty}, {md}>"
+        wpc = tuned["fp64"]["workgroups_per_cu"]
+        blocks = wl.n_elem if wpc == 0 else min(wl.n_elem, wpc * torch.cuda.get_device_properties(
+            dev).multi_processor_count)
+        grid_threads = blocks * bx * by
+    traffic = profiled_traffic(kname, grid_threads, args.workload) if grid_threads else None
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-            "kernel": "bounds_fp64_2d" if wl.dim == 2 else "bounds_fp64_1d",
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+            "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_FILE,
+            "kernel": kname, "grid_threads": grid_threads,
             "ops_per_launch": ops, "pairs_per_launch": pairs,
             "ops_per_pair": pair_ops(wl.dim), "kernel_ms": b_ms, "limit_ms": l_ms,
             "limit_hbm_frac": (2 * wl.target.nbytes + bounds.numel() * 8 + alpha.numel() * 8
@@ -281,6 +431,9 @@ def main(argv=None):
             print(f"[bench] mixed backward: {mms:.3f} ms/call, max err "
                   f"{float(diff.max()) / scale:.2e} of the max gradient", file=sys.stderr,
                   flush=True)
+    if not args.no_variants and wl.dim == 2:
+        out["variants"] = time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream,
+                                        ms_step, b_ms)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

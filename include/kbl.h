@@ -164,7 +164,9 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
  * each tile configuration that fits the velocity grid, launched either with
  * one workgroup per element or as a persistent grid of 1, 2, 4 or 8
  * workgroups per compute unit (each workgroup then walks elements in a grid
- * stride).  Timing uses the first `sample_elems` elements (all when <= 0).
+ * stride).  Timing uses the first `sample_elems` elements (all when <= 0);
+ * each candidate keeps the better of two trials, and the default launch is
+ * kept unless another candidate is more than 3% faster.
  * The choice is kept (per process) for later kbl_compute_bounds calls with
  * the same dimension, precision, grid size, nodes per element and grid mode.
  * Synchronises `stream`; leaves the full bounds of all elements in `bounds`

@@ -25,6 +25,16 @@ PREC_FP64 = 0
 PREC_MIXED_BF16 = 1
 PREC_MIXED_FP16 = 2
 PREC_MIXED_FP32 = 3
+# Launch configurations behind the tile indices of kbl_autotune_bounds
+# (FP64 2D: threads BX x BY, nodes per thread TX x TY, table mode; mixed 2D:
+# x tiles per wave, y k-steps, waves per workgroup).
+FP64_TILES = {0: (16, 16, 1, 1, 0), 1: (16, 16, 2, 2, 0), 2: (16, 16, 3, 3, 0),
+              3: (16, 16, 3, 3, 1), 4: (16, 8, 3, 6, 0), 5: (16, 16, 4, 4, 0),
+              6: (16, 16, 4, 4, 1), 7: (32, 8, 2, 8, 1), 8: (16, 16, 2, 4, 0),
+              9: (16, 16, 4, 2, 0), 10: (16, 16, 2, 2, 2), 11: (16, 16, 3, 3, 2),
+              12: (16, 16, 4, 4, 2), 13: (16, 8, 3, 6, 2)}
+MIXED_TILES = {0: (1, 1, 1), 1: (2, 2, 1), 2: (1, 2, 2), 3: (3, 3, 1), 4: (1, 3, 3),
+               5: (2, 4, 2), 6: (1, 4, 4)}
 FLAG_INDEPENDENT_ALPHA = 0x1
 FLAG_ENERGY_PERSTATE = 0x2
 

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     const int64_t nslot = p.nnz * p.n_s;
 
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {          // no addressable slots
             if (a.status && tid == 0) a.status[e] = KBL_ST_BAD_STENCIL;

@@ -106,6 +106,27 @@ struct Red {
     uint32_t flags;
 };
 
+// XCD-aware element order.  Workgroups are dispatched round-robin over the
+// XCDs (8 on MI355X, each with its own L2), so workgroup b runs on XCD b % 8.
+// Each XCD is given a contiguous range of elements, walked by its workgroups
+// in a grid stride: stencil neighbours (nearby element ids on structured and
+// locally numbered meshes) are then read through the same L2.  Every element
+// is visited exactly once for any grid size >= 1.
+constexpr int kXcds = 8;
+struct ElemRange {
+    int64_t e, end, step;
+};
+__device__ __forceinline__ ElemRange xcd_range(int64_t n) {
+    const int64_t G = gridDim.x, b = blockIdx.x;
+    const int64_t nx = G < kXcds ? G : kXcds;             // XCD groups that own workgroups
+    const int64_t x = b % nx, j = b / nx;
+    const int64_t gx = G / nx + (x < G % nx ? 1 : 0);     // workgroups in group x
+    const int64_t q = n / nx, r = n % nx;
+    const int64_t start = x * q + (x < r ? x : r);
+    const int64_t cnt = q + (x < r ? 1 : 0);
+    return ElemRange{start + j, start + cnt, gx};
+}
+
 // Ends of one state's velocity interval U -+ k sqrt(theta) (eq. truncdomain).
 // Written with an explicit fma so that every kernel rounds them identically
 // (the backward locates the extreme states by equality).

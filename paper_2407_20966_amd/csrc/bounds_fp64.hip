@@ -53,7 +53,8 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
     const int tx = tid % BX, ty = tid / BX;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
 
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
             if (tid == 0) store_nan<2>(p, e, KBL_ST_BAD_STENCIL);
@@ -223,7 +224,8 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
     const int tx = tid % BX, ty = tid / BX;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
 
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
             if (tid == 0) store_nan<2>(p, e, KBL_ST_BAD_STENCIL);
@@ -342,7 +344,8 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
     __shared__ Red red;
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
             if (tid == 0) store_nan<1>(p, e, KBL_ST_BAD_STENCIL);
@@ -411,7 +414,8 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
     __shared__ Red red;
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
             if (tid == 0) store_nan<1>(p, e, KBL_ST_BAD_STENCIL);
@@ -526,6 +530,7 @@ int default_tile_2d(int nx, int ny) {
 }  // namespace
 
 int bounds_tile_count_2d() { return kNumTiles2D; }
+int bounds_default_tile_2d(int nx, int ny) { return default_tile_2d(nx, ny); }
 
 bool bounds_tile_fits_2d(int tile, int nx, int ny) {
     if (tile < 0 || tile >= kNumTiles2D) return false;

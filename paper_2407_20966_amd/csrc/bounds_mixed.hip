@@ -141,7 +141,8 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, xr = l & 15, g = l >> 4;
 
-    for (int64_t e = blockIdx.x; e < p.n_elem; e += gridDim.x) {
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
             if (tid == 0) store_nan<2>(p, e, KBL_ST_BAD_STENCIL);
@@ -429,6 +430,7 @@ int default_mixed_tile(int nx, int ny, int precision) {
 
 int mixed_tile_count() { return kNumMixedTiles; }
 bool mixed_tile_fits_2d(int tile, int nx, int ny) { return mixed_tile_fits(tile, nx, ny); }
+int mixed_default_tile_2d(int nx, int ny, int precision) { return default_mixed_tile(nx, ny, precision); }
 
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile) {
     if (a.n_elem == 0) return hipSuccess;

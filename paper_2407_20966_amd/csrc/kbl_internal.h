@@ -70,6 +70,8 @@ hipError_t launch_bounds_fp64_energy(const BoundsArgs& a, int dim, hipStream_t s
 int bounds_tile_count_2d();
 bool bounds_tile_fits_2d(int tile, int nx, int ny);
 int mixed_tile_count();
+int bounds_default_tile_2d(int nx, int ny);
+int mixed_default_tile_2d(int nx, int ny, int precision);
 bool mixed_tile_fits_2d(int tile, int nx, int ny);
 // tile < 0 (or a tile that does not fit) selects the default for the grid size.
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);

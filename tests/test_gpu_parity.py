@@ -232,9 +232,9 @@ def test_limiter_alone_on_oracle_bounds(kbl):
 
 # every FP64 2D tile configuration (forced through the tuning knob), each on a
 # ragged grid that leaves some of its threads' nodes outside the grid
-FP64_TILE_EXTENTS = {0: (16, 16), 1: (32, 32), 2: (48, 48), 3: (48, 48), 4: (48, 48),
-                     5: (64, 64), 6: (64, 64), 7: (64, 64), 8: (32, 64), 9: (64, 32),
-                     10: (32, 32), 11: (48, 48), 12: (64, 64), 13: (48, 48)}
+from paper_2407_20966_amd._lib import FP64_TILES  # noqa: E402
+
+FP64_TILE_EXTENTS = {t: (bx * tx, by * ty) for t, (bx, by, tx, ty, _) in FP64_TILES.items()}
 
 
 @pytest.mark.parametrize("tile", sorted(FP64_TILE_EXTENTS))
