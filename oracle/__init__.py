@@ -72,6 +72,9 @@ def _load():
                                         C.c_double, C.c_int, P, P, P, C.c_double, C.c_int64,
                                         C.c_int, P, P, P, P, P, P, P, P, P]
         lib.oracle_backward.restype = C.c_int
+        lib.oracle_riemann.argtypes = [C.c_int, C.c_double, C.c_int64, C.c_int64, P, P, P, P, P,
+                                       P, P, C.c_int64, P, P]
+        lib.oracle_riemann.restype = C.c_int
         lib.oracle_delta.argtypes = [C.c_int, C.c_double]
         lib.oracle_delta.restype = C.c_double
         _lib = lib
@@ -185,6 +188,34 @@ def workload_backward(wl, grad_limited, solution=None):
     return backward(wl.dim, wl.gamma, wl.states, wl.rowptr, wl.cols, wl.n_s, g.mode,
                     g.n[: wl.dim], g.lo, g.hi, g.k, wl.r_fac,
                     wl.target if solution is None else solution, wl.node_weights, grad_limited)
+
+
+def riemann(dim: int, gamma: float, states: np.ndarray, ni: np.ndarray, nj: np.ndarray,
+            normals: np.ndarray, lam: Optional[np.ndarray] = None,
+            bounds: Optional[np.ndarray] = None, elem: Optional[np.ndarray] = None):
+    """Riemann-averaged states of Thm. 4.3 (Sec. 4) for node pairs (i, j) with
+    unit normals [d, n_pairs]; lam per pair or None for the wavespeed estimate.
+    Returns (bar [d+2, n_pairs], status [n_pairs]): bit v = below w_min,v,
+    bit d+2+v = above w_max,v of the pair's element (when bounds are given)."""
+    lib = _load()
+    states = np.ascontiguousarray(states, dtype=np.float64)
+    ni = np.ascontiguousarray(ni, dtype=np.int32)
+    nj = np.ascontiguousarray(nj, dtype=np.int32)
+    normals = np.ascontiguousarray(normals, dtype=np.float64)
+    n_pairs = ni.size
+    assert nj.size == n_pairs and normals.shape == (dim, n_pairs)
+    lam = None if lam is None else np.ascontiguousarray(lam, dtype=np.float64)
+    if bounds is not None:
+        bounds = np.ascontiguousarray(bounds, dtype=np.float64)
+        elem = np.ascontiguousarray(elem, dtype=np.int32)
+    n_elem = 0 if bounds is None else bounds.shape[1]
+    bar = np.empty((dim + 2, n_pairs), dtype=np.float64)
+    st = np.empty(n_pairs, dtype=np.uint32)
+    rc = lib.oracle_riemann(dim, gamma, n_pairs, states.shape[1], _p(states), _p(ni), _p(nj),
+                            _p(normals), _p(lam), _p(bounds), _p(elem), n_elem, _p(bar), _p(st))
+    if rc != 0:
+        raise ValueError("oracle_riemann rejected its arguments")
+    return bar, st
 
 
 def delta(dim: int, gamma: float) -> float:

@@ -30,7 +30,9 @@
  *     eq. doublelimit);
  *   - a stencil lists source units: elements (n_s nodes each) or single
  *     nodes (n_s = 1), so node-level stencils such as the solution and
- *     flux points of Sec. 5 use the same code.
+ *     flux points of Sec. 5 use the same code;
+ *   - the Riemann-averaged state of two states across a face (Thm. 4.3 of
+ *     Sec. 4) from the Euler fluxes, checked against an element's bounds.
  * OpenMP parallelises over elements only; every element is computed by one
  * thread from start to end.
  */
@@ -725,5 +727,85 @@ int oracle_backward(int d, double gamma, double r_fac, double rho_floor, double 
                                 n_elem, rowptr, cols, e, gb, gstates);
     }
     free(bnd); free(st);
+    return 0;
+}
+
+/* ------------------------------------------------ Riemann-averaged states */
+
+/* Euler flux projected on the unit normal n (Sec. 2.1). */
+static void euler_flux_n(int d, double gamma, const double* w, const double* n, double* f) {
+    const double rho = w[0];
+    const double P = pressure(d, gamma, w);
+    double un = 0.0;
+    for (int j = 0; j < d; ++j) un += (w[1 + j] / rho) * n[j];
+    f[0] = rho * un;
+    for (int j = 0; j < d; ++j) f[1 + j] = w[1 + j] * un + P * n[j];
+    f[d + 1] = (w[d + 1] + P) * un;
+}
+
+/*
+ * Riemann-averaged states of Thm. 4.3 for pairs of node states (i, j) with
+ * unit normal n_ij pointing from i to j:
+ *   wbar = (w_i + w_j)/2 - (F(w_j) - F(w_i)).n / (2 lambda),
+ * lambda given per pair, or (lam == NULL) the wavespeed estimate of the
+ * remark after the theorem, max over the two states of |U.n| + sqrt(gamma theta).
+ *   states  [d+2][n_nodes]; ni, nj [n_pairs] node ids; normals [d][n_pairs]
+ *   bounds  [2(d+2)][n_elem] and elem [n_pairs] (or NULL): bounds to test
+ *   bar     out [d+2][n_pairs]; status out [n_pairs] (or NULL): bit v if
+ *           wbar_v < w_min,v, bit d+2+v if wbar_v > w_max,v, OR_ST_INADMISSIBLE
+ *           if an input state is not admissible (wbar is then NaN)
+ * Returns 0, or -1 on bad arguments.
+ */
+int oracle_riemann(int d, double gamma, int64_t n_pairs, int64_t n_nodes, const double* states,
+                   const int* ni, const int* nj, const double* normals, const double* lam,
+                   const double* bounds, const int* elem, int64_t n_elem,
+                   double* bar, unsigned* status) {
+    if (d < 1 || d > 2 || !(gamma > 1.0)) return -1;
+    const int nv = d + 2;
+#pragma omp parallel for schedule(static)
+    for (int64_t q = 0; q < n_pairs; ++q) {
+        double wi[OR_MAXV], wj[OR_MAXV], fi[OR_MAXV], fj[OR_MAXV], n[2] = {0, 0};
+        unsigned st = 0;
+        const int64_t a = ni[q], b = nj[q];
+        int ok = a >= 0 && a < n_nodes && b >= 0 && b < n_nodes;
+        prim_t pa, pb;
+        if (ok) {
+            for (int v = 0; v < nv; ++v) {
+                wi[v] = states[(int64_t)v * n_nodes + a];
+                wj[v] = states[(int64_t)v * n_nodes + b];
+            }
+            pa = node_prim(d, gamma, states, n_nodes, a);
+            pb = node_prim(d, gamma, states, n_nodes, b);
+            ok = pa.ok && pb.ok;
+        }
+        if (!ok) {
+            for (int v = 0; v < nv; ++v) bar[(int64_t)v * n_pairs + q] = NAN;
+            if (status) status[q] = OR_ST_INADMISSIBLE;
+            continue;
+        }
+        for (int j = 0; j < d; ++j) n[j] = normals[(int64_t)j * n_pairs + q];
+        double l;
+        if (lam) l = lam[q];
+        else {
+            double ua = 0.0, ub = 0.0;
+            for (int j = 0; j < d; ++j) { ua += pa.U[j] * n[j]; ub += pb.U[j] * n[j]; }
+            double sa = fabs(ua) + sqrt(gamma * pa.theta), sb = fabs(ub) + sqrt(gamma * pb.theta);
+            l = sa > sb ? sa : sb;
+        }
+        euler_flux_n(d, gamma, wi, n, fi);
+        euler_flux_n(d, gamma, wj, n, fj);
+        for (int v = 0; v < nv; ++v) {
+            const double w = 0.5 * (wi[v] + wj[v]) - (fj[v] - fi[v]) / (2.0 * l);
+            bar[(int64_t)v * n_pairs + q] = w;
+            if (bounds && elem) {
+                const int64_t e = elem[q];
+                if (e >= 0 && e < n_elem) {
+                    if (w < bounds[(int64_t)v * n_elem + e]) st |= 1u << v;
+                    if (w > bounds[(int64_t)(nv + v) * n_elem + e]) st |= 1u << (nv + v);
+                }
+            }
+        }
+        if (status) status[q] = st;
+    }
     return 0;
 }

@@ -495,10 +495,21 @@ def make_quad_fr_workload(N: int = 64, p: int = 3, seed: int = BASE_SEED + 5,
     target = np.concatenate([T.reshape(4, n_elem, n_s), faces(T)], axis=2).reshape(4, -1)
     v_weights = np.concatenate([w2, np.zeros(4 * n1)])
     grid = GridSpec(GRID_STENCIL, (grid_nodes, grid_nodes), (0.0, 0.0), (0.0, 0.0), k)
+    # face pairs: each own flux point with the neighbour's flux point at the same
+    # place, outward unit normal, and the element whose bounds apply
+    nbr_face = [(left, 1), (right, 0), (down, 3), (up, 2)]
+    normal = [(-1.0, 0.0), (1.0, 0.0), (0.0, -1.0), (0.0, 1.0)]
+    pi = np.stack([fl(own, f) for f in range(4)], 1).reshape(n_elem, -1)
+    pj = np.stack([fl(nb, g) for nb, g in nbr_face], 1).reshape(n_elem, -1)
+    pn = np.repeat(np.array(normal)[None, :, None, :], n_elem, 0)
+    pn = np.repeat(pn, n1, 2).reshape(n_elem, 4 * n1, 2)
+    pairs = {"ni": pi.ravel().astype(np.int32), "nj": pj.ravel().astype(np.int32),
+             "normals": np.ascontiguousarray(pn.reshape(-1, 2).T),
+             "elem": np.repeat(own, 4 * n1).astype(np.int32)}
     return NodeWorkload(name, 2, gamma, n_elem, n_s, 4 * n1, np.ascontiguousarray(states),
                         rowptr, cols, np.ascontiguousarray(target), v_weights, grid, r_fac, seed,
                         {"jump_elems": np.nonzero(jumpy)[0], "face_fallback": int((~ok).sum()),
-                         "N": N})
+                         "N": N, "face_pairs": pairs})
 
 
 def make_workload(name: str, **kw) -> Workload:
