@@ -212,6 +212,29 @@ def time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream, ms_st
             "bounds_ms": fbms, "frac": fr.pairs() * 6 / (fbms * 1e-3) / VALU_PEAK_OPS}
         print(f"[bench] node-stencil FR: {msf:.3f} ms/step (bounds {fbms:.3f} ms)",
               file=sys.stderr, flush=True)
+        # Riemann-averaged states of every face pair, checked against the bounds
+        P = fr.meta["face_pairs"]
+        pni, pnj = torch.from_numpy(P["ni"]).to(dev), torch.from_numpy(P["nj"]).to(dev)
+        pn = torch.from_numpy(P["normals"]).to(dev)
+        pe = torch.from_numpy(P["elem"]).to(dev)
+        kbl.compute_bounds_nodes(fst, frp, fcl, fvg, prm1, out=fb, status=fs, stream=stream)
+        msr = _time_events(torch, stream, lambda: kbl.riemann_states(
+            fst, pni, pnj, pn, prm1, bounds=fb, elem=pe, stream=stream), steps, args.warmup)
+        _, rst = kbl.riemann_states(fst, pni, pnj, pn, prm1, bounds=fb, elem=pe, stream=stream)
+        torch.cuda.synchronize()
+        npairs = int(pni.numel())
+        # bytes per pair: two gathered states, ids, normal, element id, the
+        # element's bounds, the averaged state and the status written
+        bpp = 2 * 4 * 8 + 2 * 4 + 2 * 8 + 4 + 8 * 8 + 4 * 8 + 4
+        out["riemann_states_fr"] = {
+            "pairs": npairs, "ms": msr, "pairs_per_s": npairs / (msr * 1e-3),
+            "hbm_frac_upper": npairs * bpp / (msr * 1e-3) / HBM_PEAK,
+            "outside_bounds": int((rst != 0).sum().item()),
+            "what": "Riemann-averaged state (Thm. 4.3) of every flux-point pair, wavespeed "
+                    "estimate, checked against the element bounds"}
+        print(f"[bench] riemann states: {msr:.3f} ms for {npairs} pairs, "
+              f"{out['riemann_states_fr']['outside_bounds']} outside the bounds",
+              file=sys.stderr, flush=True)
         del fst, ftg, flim
     print(f"[bench] variants: energy {ms:.3f} ms, strict {ms0:.3f} ms/step, independent limit "
           f"{msi:.3f} ms", file=sys.stderr, flush=True)

@@ -208,6 +208,37 @@ kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int3
                      const double* node_weights, double* limited, double* alpha,
                      uint32_t* elem_status, void* stream);
 
+/* Status bits of kbl_riemann_states, per pair. */
+#define KBL_RS_BELOW(v)   (1u << (v))        /* wbar_v < w_min,v of the pair's element */
+#define KBL_RS_ABOVE(v)   (1u << (8 + (v)))  /* wbar_v > w_max,v */
+#define KBL_RS_BAD_INPUT  (1u << 16)         /* node id out of range or state not admissible */
+
+/*
+ * kbl_riemann_states - Riemann-averaged states of Thm. 4.3 (Sec. 4) for pairs
+ * of node states across faces, and their position relative to the bounds:
+ *   wbar = (w_i + w_j)/2 - (F(w_j) - F(w_i)).n / (2 lambda)
+ * with the Euler flux F (Sec. 2.1).  The theorem places wbar in the bounds
+ * of any stencil holding both states when lambda bounds the particle speeds
+ * of the velocity domain; the remark after it uses the macroscopic wavespeed
+ * estimate instead.  FP64.
+ *
+ *   states       [d+2][n_nodes] conserved node states.
+ *   node_i, node_j [n_pairs] node ids (i on the element side, j across).
+ *   normals      [d][n_pairs] unit normals pointing from i to j.
+ *   lambda       [n_pairs] wavespeed bounds, or NULL for
+ *                max(|U_i.n| + sqrt(gamma theta_i), |U_j.n| + sqrt(gamma theta_j)).
+ *   bounds, elem [2(d+2)][n_elem] bounds and [n_pairs] element of each pair
+ *                (both NULL to skip the check).
+ *   bar          out [d+2][n_pairs]; NaN for KBL_RS_BAD_INPUT pairs.
+ *   pair_status  out [n_pairs] KBL_RS_* bits, or NULL.
+ * All arrays are device memory; only params->gamma is used.
+ */
+kbl_status kbl_riemann_states(const kbl_params* params, int32_t dim, int64_t n_pairs,
+                              int64_t n_nodes, const double* states, const int32_t* node_i,
+                              const int32_t* node_j, const double* normals,
+                              const double* lambda, const double* bounds, const int32_t* elem,
+                              int64_t n_elem, double* bar, uint32_t* pair_status, void* stream);
+
 /*
  * kbl_backward_workspace_bytes - device workspace kbl_bounds_limit_backward
  * needs: the recomputed forward bounds and status, dJ/dbounds, and one

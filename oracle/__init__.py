@@ -196,7 +196,8 @@ def riemann(dim: int, gamma: float, states: np.ndarray, ni: np.ndarray, nj: np.n
     """Riemann-averaged states of Thm. 4.3 (Sec. 4) for node pairs (i, j) with
     unit normals [d, n_pairs]; lam per pair or None for the wavespeed estimate.
     Returns (bar [d+2, n_pairs], status [n_pairs]): bit v = below w_min,v,
-    bit d+2+v = above w_max,v of the pair's element (when bounds are given)."""
+    bit 8+v = above w_max,v of the pair's element (when bounds are given),
+    bit 16 = bad node id or inadmissible input state."""
     lib = _load()
     states = np.ascontiguousarray(states, dtype=np.float64)
     ni = np.ascontiguousarray(ni, dtype=np.int32)

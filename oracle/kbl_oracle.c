@@ -752,8 +752,9 @@ static void euler_flux_n(int d, double gamma, const double* w, const double* n, 
  *   states  [d+2][n_nodes]; ni, nj [n_pairs] node ids; normals [d][n_pairs]
  *   bounds  [2(d+2)][n_elem] and elem [n_pairs] (or NULL): bounds to test
  *   bar     out [d+2][n_pairs]; status out [n_pairs] (or NULL): bit v if
- *           wbar_v < w_min,v, bit d+2+v if wbar_v > w_max,v, OR_ST_INADMISSIBLE
- *           if an input state is not admissible (wbar is then NaN)
+ *           wbar_v < w_min,v, bit 8+v if wbar_v > w_max,v, bit 16 if a node
+ *           id is out of range or an input state is not admissible (wbar is
+ *           then NaN)
  * Returns 0, or -1 on bad arguments.
  */
 int oracle_riemann(int d, double gamma, int64_t n_pairs, int64_t n_nodes, const double* states,
@@ -780,7 +781,7 @@ int oracle_riemann(int d, double gamma, int64_t n_pairs, int64_t n_nodes, const 
         }
         if (!ok) {
             for (int v = 0; v < nv; ++v) bar[(int64_t)v * n_pairs + q] = NAN;
-            if (status) status[q] = OR_ST_INADMISSIBLE;
+            if (status) status[q] = 1u << 16;
             continue;
         }
         for (int j = 0; j < d; ++j) n[j] = normals[(int64_t)j * n_pairs + q];
@@ -801,7 +802,7 @@ int oracle_riemann(int d, double gamma, int64_t n_pairs, int64_t n_nodes, const 
                 const int64_t e = elem[q];
                 if (e >= 0 && e < n_elem) {
                     if (w < bounds[(int64_t)v * n_elem + e]) st |= 1u << v;
-                    if (w > bounds[(int64_t)(nv + v) * n_elem + e]) st |= 1u << (nv + v);
+                    if (w > bounds[(int64_t)(nv + v) * n_elem + e]) st |= 1u << (8 + v);
                 }
             }
         }

@@ -7,15 +7,15 @@ loudly if it has not been built.
 """
 
 from ._lib import (  # noqa: F401
-    GRID_GLOBAL, GRID_STENCIL, PREC_FP64, PREC_MIXED_BF16, PREC_MIXED_FP16, PREC_MIXED_FP32,
+    RS_BAD_INPUT, GRID_GLOBAL, GRID_STENCIL, PREC_FP64, PREC_MIXED_BF16, PREC_MIXED_FP16, PREC_MIXED_FP32,
     ST_INADMISSIBLE, ST_RHO_FLOOR, ST_EPS_RULE, ST_LIMITED, ST_PSTEP, ST_PMEAN_FLOOR,
     ST_MEAN_OUTSIDE, ST_BAD_BOUNDS, ST_BAD_STENCIL, ST_TOO_LARGE, ST_ASYMMETRIC, KblError,
     LIB_PATH,
 )
 from .ops import (  # noqa: F401
     KineticBoundsLimit, autotune_bounds, bounds_and_limit, bounds_limit_backward,
-    compute_bounds, compute_bounds_nodes, limit, make_params, make_vgrid,
+    compute_bounds, compute_bounds_nodes, limit, make_params, make_vgrid, riemann_states,
 )
 
-__all__ = ["compute_bounds", "compute_bounds_nodes", "limit", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
+__all__ = ["compute_bounds", "compute_bounds_nodes", "limit", "riemann_states", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
            "KineticBoundsLimit", "make_params", "make_vgrid", "KblError"]

@@ -35,6 +35,7 @@ FP64_TILES = {0: (16, 16, 1, 1, 0), 1: (16, 16, 2, 2, 0), 2: (16, 16, 3, 3, 0),
               12: (16, 16, 4, 4, 2), 13: (16, 8, 3, 6, 2)}
 MIXED_TILES = {0: (1, 1, 1), 1: (2, 2, 1), 2: (1, 2, 2), 3: (3, 3, 1), 4: (1, 3, 3),
                5: (2, 4, 2), 6: (1, 4, 4)}
+RS_BAD_INPUT = 1 << 16
 FLAG_INDEPENDENT_ALPHA = 0x1
 FLAG_ENERGY_PERSTATE = 0x2
 
@@ -102,6 +103,9 @@ def _load():
                                                  C.c_int64, C.c_int64, P, P, P, C.POINTER(VGrid),
                                                  P, P, P]
         lib.kbl_compute_bounds_nodes.restype = C.c_int
+        lib.kbl_riemann_states.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int64,
+                                           P, P, P, P, P, P, P, C.c_int64, P, P, P]
+        lib.kbl_riemann_states.restype = C.c_int
         lib.kbl_autotune_bounds.argtypes = [C.POINTER(Params), C.c_int32, C.c_int64, C.c_int32,
                                             C.c_int64, P, P, P, C.POINTER(VGrid), P, P,
                                             C.c_int64, P]

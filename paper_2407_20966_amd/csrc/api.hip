@@ -348,6 +348,38 @@ kbl_status kbl_limit(const kbl_params* params, int32_t dim, int64_t n_elem, int3
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 
+kbl_status kbl_riemann_states(const kbl_params* params, int32_t dim, int64_t n_pairs,
+                              int64_t n_nodes, const double* states, const int32_t* node_i,
+                              const int32_t* node_j, const double* normals,
+                              const double* lambda, const double* bounds, const int32_t* elem,
+                              int64_t n_elem, double* bar, uint32_t* pair_status, void* stream) {
+    double half_delta = 0.0;
+    kbl_status rc = check_params(params, dim, &half_delta);
+    if (rc != KBL_OK) return rc;
+    if (n_pairs < 0 || n_nodes < 0 || n_elem < 0) return KBL_ERR_ARG;
+    if (n_pairs > 0 && (!states || !node_i || !node_j || !normals || !bar)) return KBL_ERR_ARG;
+    if ((bounds == nullptr) != (elem == nullptr)) return KBL_ERR_ARG;
+    if (bounds && n_elem < 1) return KBL_ERR_ARG;
+    kbl::RiemannArgs r;
+    memset(&r, 0, sizeof(r));
+    r.states = states;
+    r.n_nodes = n_nodes;
+    r.ni = node_i;
+    r.nj = node_j;
+    r.normals = normals;
+    r.lam = lambda;
+    r.bounds = bounds;
+    r.elem = elem;
+    r.n_elem = n_elem;
+    r.bar = bar;
+    r.status = pair_status;
+    r.n_pairs = n_pairs;
+    r.gamma = params->gamma;
+    r.gm1 = params->gamma - 1.0;
+    hipError_t err = kbl::launch_riemann_fp64(r, dim, (hipStream_t)stream);
+    return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
 size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, int64_t nnz) {
     if ((dim != 1 && dim != 2) || n_elem < 0 || n_s < 1 || nnz < 0) return 0;
     const size_t nv = (size_t)dim + 2;

@@ -61,6 +61,24 @@ struct LimitArgs {
     double c[kMaxLimitNodes];        // element mean weights (>= 0, positive sum)
 };
 
+// Arguments of the Riemann-averaged state kernel.
+struct RiemannArgs {
+    const double* states;
+    int64_t n_nodes;
+    const int32_t* ni;
+    const int32_t* nj;
+    const double* normals;    // [d][n_pairs]
+    const double* lam;        // [n_pairs] or null (wavespeed estimate)
+    const double* bounds;     // [2(d+2)][n_elem] or null
+    const int32_t* elem;      // [n_pairs] or null
+    int64_t n_elem;
+    double* bar;              // [d+2][n_pairs]
+    uint32_t* status;         // [n_pairs] or null
+    int64_t n_pairs;
+    double gamma;
+    double gm1;
+};
+
 // Host-side launchers (one per translation unit).  They return hipSuccess or
 // the launch error; argument checking happened before.
 // tile < 0 selects the default 2D tile for the grid size.
@@ -76,6 +94,7 @@ bool mixed_tile_fits_2d(int tile, int nx, int ny);
 // tile < 0 (or a tile that does not fit) selects the default for the grid size.
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
+hipError_t launch_riemann_fp64(const RiemannArgs& a, int dim, hipStream_t stream);
 // Bounds backward + gather.  mixed: winners from the FP32 envelopes of the
 // mixed-precision forward (2D only); everything else stays FP64.
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,

@@ -131,6 +131,39 @@ def compute_bounds_nodes(states: torch.Tensor, rowptr: torch.Tensor, cols: torch
     return out, status
 
 
+def riemann_states(states: torch.Tensor, node_i: torch.Tensor, node_j: torch.Tensor,
+                   normals: torch.Tensor, params: L.Params, lam: Optional[torch.Tensor] = None,
+                   bounds: Optional[torch.Tensor] = None, elem: Optional[torch.Tensor] = None,
+                   stream=None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Riemann-averaged states (Thm. 4.3) of node pairs and their KBL_RS_* status
+    against the bounds of each pair's element (see kbl_riemann_states)."""
+    _check(states, "states", torch.float64)
+    dev = states.device
+    _check(node_i, "node_i", torch.int32, dev)
+    _check(node_j, "node_j", torch.int32, dev)
+    _check(normals, "normals", torch.float64, dev)
+    dim = states.shape[0] - 2
+    n_pairs = node_i.numel()
+    if node_j.numel() != n_pairs or tuple(normals.shape) != (dim, n_pairs):
+        raise ValueError("node_j/normals do not match node_i")
+    if lam is not None:
+        _check(lam, "lam", torch.float64, dev)
+    n_elem = 0
+    if bounds is not None:
+        _check(bounds, "bounds", torch.float64, dev)
+        _check(elem, "elem", torch.int32, dev)
+        n_elem = bounds.shape[1]
+    bar = torch.empty((dim + 2, n_pairs), dtype=torch.float64, device=dev)
+    status = torch.empty(n_pairs, dtype=torch.int32, device=dev)
+    rc = L.lib().kbl_riemann_states(C.byref(params), dim, n_pairs, states.shape[1], _ptr(states),
+                                    _ptr(node_i), _ptr(node_j), _ptr(normals), _ptr(lam),
+                                    _ptr(bounds), _ptr(elem), n_elem, _ptr(bar), _ptr(status),
+                                    _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_riemann_states")
+    return bar, status
+
+
 def autotune_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor, n_s: int,
                     vgrid: L.VGrid, params: L.Params, sample_elems: int = 32768,
                     stream=None) -> int:

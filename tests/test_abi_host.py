@@ -30,7 +30,8 @@ def test_header_declares_expected_entry_points():
     syms = L.header_symbols()
     for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
               "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes",
-              "kbl_autotune_bounds", "kbl_autotune_clear", "kbl_compute_bounds_nodes"):
+              "kbl_autotune_bounds", "kbl_autotune_clear", "kbl_compute_bounds_nodes",
+              "kbl_riemann_states"):
         assert s in syms
 
 
@@ -241,3 +242,20 @@ def test_backward_default_method_only(lib):
     g = _grid()
     for flags in (L.FLAG_INDEPENDENT_ALPHA, L.FLAG_ENERGY_PERSTATE):
         assert _backward(lib, _params(lib, flags=flags), g) == L.KBL_ERR_UNSUPPORTED
+
+
+def _riemann(lib, p, dim=2, n_pairs=4, n_nodes=8, bounds=None, elem=None, n_elem=0, ptrs=True):
+    P = FAKE if ptrs else None
+    return lib.kbl_riemann_states(C.byref(p), dim, n_pairs, n_nodes, P, P, P, P, None, bounds,
+                                  elem, n_elem, P, None, None)
+
+
+def test_riemann_rejects_bad_arguments(lib):
+    p = _params(lib)
+    assert _riemann(lib, p, dim=3) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, n_pairs=-1) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, ptrs=False) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, bounds=FAKE, elem=None, n_elem=4) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, bounds=FAKE, elem=FAKE, n_elem=0) == L.KBL_ERR_ARG
+    assert _riemann(lib, _params(lib, 1.0)) == L.KBL_ERR_GAMMA
+    assert _riemann(lib, p, n_pairs=0, ptrs=False) == L.KBL_OK      # nothing to do, no launch
