@@ -141,12 +141,12 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int x = TX * tx + i;
-            ux[i] = box[0] + (x < p.nx ? x : p.nx - 1) * hx;
+            ux[i] = node_pos(box[0], x < p.nx ? x : p.nx - 1, hx);
         }
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int y = TY * ty + j;
-            uy[j] = D == 2 ? box[2] + (y < p.ny ? y : p.ny - 1) * hy : 0.0;
+            uy[j] = D == 2 ? node_pos(box[2], y < p.ny ? y : p.ny - 1, hy) : 0.0;
         }
         // envelopes and their winners: Tmin, Tmax, Imin, Imax
         double q[4][TX][TY];

@@ -38,8 +38,12 @@ __device__ __forceinline__ Prim load_prim(const BoundsArgs& p, int64_t node) {
     const double mx = p.states[p.n_nodes + node];
     const double my = (D == 2) ? p.states[2 * p.n_nodes + node] : 0.0;
     const double E = p.states[(D + 1) * p.n_nodes + node];
-    const double mm = (D == 2) ? mx * mx + my * my : mx * mx;
-    const double P = p.gm1 * (E - 0.5 * mm / rho);
+    double mm, P;
+    {
+#pragma clang fp contract(off)
+        mm = (D == 2) ? mx * mx + my * my : mx * mx;
+        P = p.gm1 * (E - 0.5 * mm / rho);
+    }
     s.rho = rho;
     s.ux = mx / rho;
     s.uy = (D == 2) ? my / rho : 0.0;
@@ -130,8 +134,24 @@ __device__ __forceinline__ ElemRange xcd_range(int64_t n) {
 // Ends of one state's velocity interval U -+ k sqrt(theta) (eq. truncdomain).
 // Written with an explicit fma so that every kernel rounds them identically
 // (the backward locates the extreme states by equality).
-__device__ __forceinline__ double box_lo(double u, double k, double sd) { return fma(-k, sd, u); }
-__device__ __forceinline__ double box_hi(double u, double k, double sd) { return fma(k, sd, u); }
+// Rounded like the plain definition (no fused multiply-add), as are the
+// node positions and the primitive variables below: values deep in the
+// Maxwellian tails are very sensitive to the node positions (d q / d u =
+// -(u - U)/theta), so the box ends and nodes are kept bit-identical to the
+// straightforward evaluation.
+__device__ __forceinline__ double box_lo(double u, double k, double sd) {
+#pragma clang fp contract(off)
+    return u - k * sd;
+}
+__device__ __forceinline__ double box_hi(double u, double k, double sd) {
+#pragma clang fp contract(off)
+    return u + k * sd;
+}
+// Velocity node j of a trapezoid grid starting at lo with spacing h.
+__device__ __forceinline__ double node_pos(double lo, int j, double h) {
+#pragma clang fp contract(off)
+    return lo + (double)j * h;
+}
 
 // Per-state coefficients of the log-Maxwellian (Sec. 2.2, Sec. 3.6).
 struct Coef {

@@ -76,12 +76,12 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int j = tx + BX * i;
-            ux[i] = lox + (j < p.nx ? j : p.nx - 1) * hx;
+            ux[i] = node_pos(lox, j < p.nx ? j : p.nx - 1, hx);
         }
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int jj = ty + BY * j;
-            uy[j] = loy + (jj < p.ny ? jj : p.ny - 1) * hy;
+            uy[j] = node_pos(loy, jj < p.ny ? jj : p.ny - 1, hy);
         }
 
         double qtn[TX][TY], qtx[TX][TY], qin[TX][TY], qix[TX][TY];
@@ -102,7 +102,7 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
                     for (int idx = tid; idx < tn * NYM; idx += NT) {
                         const int s = idx / NYM, j = idx - s * NYM;
                         const int jc = j < p.ny ? j : p.ny - 1;
-                        const double d = (loy + jc * hy) - sC[t0 + s].uy;
+                        const double d = node_pos(loy, jc, hy) - sC[t0 + s].uy;
                         sB[s][j] = (sC[t0 + s].nk * d) * d;
                     }
                     if (BTAB == 2) {
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
                             const int s = idx / NXM, i = idx - s * NXM;
                             const int ic = i < p.nx ? i : p.nx - 1;
                             const Coef& c = sC[t0 + s];
-                            const double d = (lox + ic * hx) - c.ux;
+                            const double d = node_pos(lox, ic, hx) - c.ux;
                             const double t = c.nk * d;
                             sA[2 * s][i] = fma(t, d, c.a);
                             sA[2 * s + 1][i] = fma(t, d, c.al);
@@ -245,13 +245,13 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int j = tx + BX * i;
-            ux[i] = lox + (j < p.nx ? j : p.nx - 1) * hx;
+            ux[i] = node_pos(lox, j < p.nx ? j : p.nx - 1, hx);
             hux[i] = 0.5 * ux[i] * ux[i];
         }
 #pragma unroll
         for (int j = 0; j < TY; ++j) {
             const int jj = ty + BY * j;
-            uy[j] = loy + (jj < p.ny ? jj : p.ny - 1) * hy;
+            uy[j] = node_pos(loy, jj < p.ny ? jj : p.ny - 1, hy);
             huy[j] = 0.5 * uy[j] * uy[j];
         }
         double gn[TX][TY], gx[TX][TY], en[TX][TY], ex[TX][TY];
@@ -272,14 +272,14 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
                     const int s = idx / NXM, i = idx - s * NXM;
                     const int ic = i < p.nx ? i : p.nx - 1;
                     const Coef& c = sC[t0 + s];
-                    const double d = (lox + ic * hx) - c.ux;
+                    const double d = node_pos(lox, ic, hx) - c.ux;
                     sEA[s][i] = exp(fma(c.nk * d, d, c.a));
                 }
                 for (int idx = tid; idx < tn * NYM; idx += NT) {
                     const int s = idx / NYM, j = idx - s * NYM;
                     const int jc = j < p.ny ? j : p.ny - 1;
                     const Coef& c = sC[t0 + s];
-                    const double d = (loy + jc * hy) - c.uy;
+                    const double d = node_pos(loy, jc, hy) - c.uy;
                     sEB[s][j] = exp((c.nk * d) * d);
                 }
                 for (int s = tid; s < tn; s += NT) sCs[s] = p.half_delta * (-0.5 / sC[t0 + s].nk);
@@ -364,7 +364,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             const int j = tid + NT * i;
-            u[i] = lo + (j < p.nx ? j : p.nx - 1) * h;
+            u[i] = node_pos(lo, j < p.nx ? j : p.nx - 1, h);
             hu[i] = 0.5 * u[i] * u[i];
             gn[i] = kInf; gx[i] = -kInf; en[i] = kInf; ex[i] = -kInf;
         }
@@ -434,7 +434,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             const int j = tid + NT * i;
-            u[i] = lo + (j < p.nx ? j : p.nx - 1) * h;
+            u[i] = node_pos(lo, j < p.nx ? j : p.nx - 1, h);
             qtn[i] = kInf; qtx[i] = -kInf; qin[i] = kInf; qix[i] = -kInf;
         }
         for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {

@@ -107,7 +107,7 @@ struct XF {
 __device__ __forceinline__ XF x_factors(const BoundsArgs& p, const double* box, double hx, int x) {
     XF f = {0.0, 0.0, 0.0, 0.0};
     if (x < p.nx) {
-        const double u = box[0] + x * hx;
+        const double u = node_pos(box[0], x, hx);
         f.w = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
         f.m = u < 0.0 ? f.w * u : 0.0;
         f.p = u < 0.0 ? 0.0 : f.w * u;
@@ -184,7 +184,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
 #pragma unroll
         for (int i = 0; i < TXW; ++i) {
             const int x = 16 * (w + NW * i) + xr;
-            uxc[i] = (float)((box[0] + (x < p.nx ? x : p.nx - 1) * hx) - cx);
+            uxc[i] = (float)(node_pos(box[0], x < p.nx ? x : p.nx - 1, hx) - cx);
         }
         float tn[TXW][TY], tX[TXW][TY], in_[TXW][TY], iX[TXW][TY];
 #pragma unroll
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             __syncthreads();
             for (int idx = tid; idx < cn * NY; idx += NT) {
                 const int s = idx / NY, j = idx - s * NY;
-                const float uyc = (float)((box[2] + (j < p.ny ? j : p.ny - 1) * hy) - cy);
+                const float uyc = (float)(node_pos(box[2], j < p.ny ? j : p.ny - 1, hy) - cy);
                 const float d = uyc - sF[c0 + s].uy;
                 stage.b[s][j] = (sF[c0 + s].nk * d) * d;
             }
@@ -269,7 +269,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                     const int ty = 16 * (j / 4) + 4 * g + (j % 4);
                     float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f;
                     if (ty < p.ny) {
-                        const double u = box[2] + ty * hy;
+                        const double u = node_pos(box[2], ty, hy);
                         const double a0 = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
                         y0 = (float)a0;
                         y1 = (float)(u < 0.0 ? a0 * u : 0.0);
@@ -313,7 +313,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                 const int ty = 16 * (j / 4) + 4 * g + (j % 4);
                 double v = 0.0;
                 if (ty < p.ny && xr < 4) {
-                    const double u = box[2] + ty * hy;
+                    const double u = node_pos(box[2], ty, hy);
                     const double wy = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
                     v = xr == 0 ? wy
                       : xr == 1 ? (u < 0.0 ? wy * u : 0.0)

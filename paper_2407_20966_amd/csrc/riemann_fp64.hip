@@ -54,8 +54,9 @@ __global__ __launch_bounds__(256) void riemann_fp64(RiemannArgs a) {
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < a.n_pairs;
          q += (int64_t)gridDim.x * 256) {
         double wi[NV], wj[NV], Ui[2] = {0, 0}, Uj[2] = {0, 0}, Pi, Pj;
-        const bool ok = load_state<D>(a, a.ni[q], wi, Ui, &Pi) &
-                        load_state<D>(a, a.nj[q], wj, Uj, &Pj);
+        const bool ok_i = load_state<D>(a, a.ni[q], wi, Ui, &Pi);
+        const bool ok_j = load_state<D>(a, a.nj[q], wj, Uj, &Pj);
+        const bool ok = ok_i && ok_j;
         if (!ok) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) a.bar[(int64_t)v * a.n_pairs + q] = __longlong_as_double(0x7ff8000000000000LL);
