@@ -53,7 +53,7 @@ WORKLOAD_TEXT = {
 KERNEL_SOURCES = ("paper_2407_20966_amd/csrc/bounds_fp64.hip",
                   "paper_2407_20966_amd/csrc/bounds_common.h",
                   "paper_2407_20966_amd/csrc/kbl_internal.h")
-TRAFFIC_FILE = "profiles/bounds_fp64_2d_quad256_traffic.txt"
+TRAFFIC_FILE = "profiles/bounds_fp64_2d_traffic.txt"
 
 
 def kernel_sources_sha() -> str:
@@ -68,23 +68,34 @@ def kernel_sources_sha() -> str:
 
 def profiled_traffic(kernel: str, grid_threads: int, workload: str):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, scaled by the copy-kernel calibration), or None when the
-    summary is for another kernel, launch shape or workload, or the kernel's
+    WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is
+    no entry for this kernel, launch shape and workload, or the kernel's
     sources changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
-    kv = {}
+    head, entries, cur = {}, [], None
     for line in open(path):
-        if "=" in line and not line.lstrip().startswith("#"):
+        line = line.strip()
+        if not line or line.startswith("#"):
+            continue
+        if line == "[entry]":
+            cur = {}
+            entries.append(cur)
+            continue
+        if "=" in line:
             k, v = line.split("=", 1)
-            kv[k.strip()] = v.strip()
-    try:
-        same = (kv["kernel"] == kernel and int(kv["grid_threads"]) == grid_threads
-                and kv["workload"] == workload and kv["source_sha256"] == kernel_sources_sha())
-        return float(kv["bytes_per_launch"]) if same else None
-    except (KeyError, ValueError):
+            (head if cur is None else cur)[k.strip()] = v.strip()
+    if head.get("source_sha256") != kernel_sources_sha():
         return None
+    for e in entries:
+        try:
+            if (e["kernel"] == kernel and int(e["grid_threads"]) == grid_threads
+                    and e["workload"] == workload):
+                return float(e["bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def pair_ops(dim: int) -> int:
