@@ -159,6 +159,15 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
                                     uint32_t* elem_status, void* stream);
 
 /*
+ * Tuning knobs read from the environment at each kbl_compute_bounds call
+ * (meant for measurements and tests; they override kbl_autotune_bounds):
+ *   KBL_BOUNDS_TILE=<t>        FP64 2D tile configuration index (ignored if
+ *                              it does not cover the velocity grid)
+ *   KBL_MIXED_TILE=<t>         mixed-precision tile configuration index
+ *   KBL_PERSISTENT_BLOCKS=<g>  grid of g workgroups walking the elements
+ *                              (0 = one workgroup per element)
+ */
+/*
  * kbl_autotune_bounds - picks the launch configuration of kbl_compute_bounds
  * for this problem shape by timing every candidate on the caller's inputs:
  * each tile configuration that fits the velocity grid, launched either with
