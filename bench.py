@@ -109,21 +109,28 @@ def pair_ops(dim: int) -> int:
 
 
 def cpu_baseline(wl, target_s: float = 12.0):
+    """The oracle (bounds + limit) on a seeded element sample of the workload,
+    sized to take about target_s of wall time on the host cores."""
     import oracle
     oracle.build(force=False)
     rng = np.random.default_rng(12345)
-    # calibrate on a small sample, then run ~target_s of wall time
-    probe = np.sort(rng.choice(wl.n_elem, min(32, wl.n_elem), replace=False))
-    t0 = time.perf_counter()
-    rb, _ = oracle.workload_bounds(wl, elems=probe)
-    oracle.workload_limit(wl, rb, elems=probe)
-    dt = time.perf_counter() - t0
-    n = int(min(wl.n_elem, max(64, len(probe) * target_s / max(dt, 1e-6))))
-    sample = np.sort(rng.choice(wl.n_elem, n, replace=False))
-    t0 = time.perf_counter()
-    rb, _ = oracle.workload_bounds(wl, elems=sample)
-    oracle.workload_limit(wl, rb, elems=sample)
-    dt = time.perf_counter() - t0
+
+    def run(n):
+        sample = np.sort(rng.choice(wl.n_elem, n, replace=False))
+        t0 = time.perf_counter()
+        rb, _ = oracle.workload_bounds(wl, elems=sample)
+        oracle.workload_limit(wl, rb, elems=sample)
+        return time.perf_counter() - t0
+
+    # grow the calibration sample until it takes at least a second, then size
+    n, dt = 64, 0.0
+    while n < wl.n_elem:
+        dt = run(n)
+        if dt >= 1.0:
+            break
+        n = min(wl.n_elem, n * 4)
+    n = int(min(wl.n_elem, max(64, n * target_s / max(dt, 1e-6))))
+    dt = run(n)
     cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
     return {"value": n / dt, "unit": "elements/s", "cores": cores, "kind": "oracle",
             "sample": f"{n} seeded random elements of the same workload (bounds + limit), "
