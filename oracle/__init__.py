@@ -110,9 +110,9 @@ def bounds(dim: int, gamma: float, states: np.ndarray, rowptr: np.ndarray,
         n_sel = elems.size
     else:
         n_sel = n_elem
-    n_arr = np.array(list(n) + [2] * (2 - len(n)), dtype=np.int32)[:2]
-    lo_arr = np.array(list(lo) + [0.0] * (2 - len(lo)), dtype=np.float64)[:2]
-    hi_arr = np.array(list(hi) + [0.0] * (2 - len(hi)), dtype=np.float64)[:2]
+    n_arr = np.array(list(n) + [2] * (3 - len(n)), dtype=np.int32)[:3]
+    lo_arr = np.array(list(lo) + [0.0] * (3 - len(lo)), dtype=np.float64)[:3]
+    hi_arr = np.array(list(hi) + [0.0] * (3 - len(hi)), dtype=np.float64)[:3]
     out = np.empty((2 * (dim + 2), n_sel), dtype=np.float64)
     st = np.empty(n_sel, dtype=np.uint32)
     rc = lib.oracle_bounds(dim, gamma, r_fac, rho_floor, grid_mode, _p(n_arr), _p(lo_arr),
@@ -169,9 +169,9 @@ def backward(dim, gamma, states, rowptr, cols, n_s, grid_mode, n, lo, hi, k, r_f
     cols = np.ascontiguousarray(cols, dtype=np.int32)
     c = np.ascontiguousarray(node_weights, dtype=np.float64)
     n_elem = rowptr.size - 1
-    n_arr = np.array(list(n) + [2] * (2 - len(n)), dtype=np.int32)[:2]
-    lo_arr = np.array(list(lo) + [0.0] * (2 - len(lo)), dtype=np.float64)[:2]
-    hi_arr = np.array(list(hi) + [0.0] * (2 - len(hi)), dtype=np.float64)[:2]
+    n_arr = np.array(list(n) + [2] * (3 - len(n)), dtype=np.int32)[:3]
+    lo_arr = np.array(list(lo) + [0.0] * (3 - len(lo)), dtype=np.float64)[:3]
+    hi_arr = np.array(list(hi) + [0.0] * (3 - len(hi)), dtype=np.float64)[:3]
     gsol = np.empty_like(solution)
     gst = np.empty_like(states)
     gb = np.empty((2 * (dim + 2), n_elem), dtype=np.float64)

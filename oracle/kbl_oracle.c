@@ -8,6 +8,7 @@
  * load.  The product library never links or calls it, and it shares no code,
  * header or constant with the HIP path.
  *
+ * Dimensions d = 1, 2, 3 (the backward: d <= 2).
  * Everything is written the slow, literal way on purpose:
  *   - each stencil state's Maxwellian is evaluated in its direct form
  *     rho (2 pi theta)^(-d/2) exp(-|u-U|^2 / (2 theta))  (Sec. 2.2, eq. maxwell)
@@ -51,7 +52,7 @@
 #define OR_ST_BAD_BOUNDS   0x80u  /* bounds not finite: element passed through */
 #define OR_ST_BAD_STENCIL  0x100u /* stencil row empty or out of range: bounds are NaN */
 
-#define OR_MAXV 4                 /* d+2 for d<=2 */
+#define OR_MAXV 5                 /* d+2 for d<=3 */
 
 /* ---------------------------------------------------------------- helpers */
 
@@ -78,14 +79,14 @@ double oracle_delta(int d, double gamma) {
 }
 
 /* Primitive state of one node: rho, U, theta = P/rho (Sec. 2.1, 2.2). */
-typedef struct { double rho, U[2], theta; int ok; } prim_t;
+typedef struct { double rho, U[3], theta; int ok; } prim_t;
 
 static prim_t node_prim(int d, double gamma, const double* states, int64_t n_nodes, int64_t node) {
     prim_t p;
     double w[OR_MAXV];
     for (int v = 0; v < d + 2; ++v) w[v] = states[(int64_t)v * n_nodes + node];
     p.rho = w[0];
-    p.U[0] = p.U[1] = 0.0;
+    p.U[0] = p.U[1] = p.U[2] = 0.0;
     for (int j = 0; j < d; ++j) p.U[j] = w[1 + j] / w[0];
     double P = pressure(d, gamma, w);
     p.theta = P / w[0];
@@ -147,7 +148,7 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
     const double delta = oracle_delta(d, gamma);
 
     /* Velocity box (Sec. 3.7, eq. truncdomain) and trapezoid spacing. */
-    double lo[2] = {0, 0}, hi[2] = {0, 0}, h[2] = {0, 0};
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, h[3] = {0, 0, 0};
     for (int j = 0; j < d; ++j) {
         if (grid_mode == 0) { lo[j] = lo_in[j]; hi[j] = hi_in[j]; }
         else {
@@ -163,13 +164,15 @@ static unsigned element_bounds(int d, double gamma, double r_fac, double rho_flo
     }
 
     nsum rmin = {0, 0}, rmax = {0, 0}, emin = {0, 0}, emax = {0, 0};
-    nsum mmin[2] = {{0, 0}, {0, 0}}, mmax[2] = {{0, 0}, {0, 0}};
-    const int n1 = (d == 2) ? n[1] : 1;
+    nsum mmin[3] = {{0, 0}, {0, 0}, {0, 0}}, mmax[3] = {{0, 0}, {0, 0}, {0, 0}};
+    const int n1 = (d >= 2) ? n[1] : 1;
+    const int n2 = (d >= 3) ? n[2] : 1;
 
+    for (int tz = 0; tz < n2; ++tz)
     for (int ty = 0; ty < n1; ++ty)
         for (int tx = 0; tx < n[0]; ++tx) {
-            int t[2] = {tx, ty};
-            double u[2] = {0, 0}, M = 1.0;
+            int t[3] = {tx, ty, tz};
+            double u[3] = {0, 0, 0}, M = 1.0;
             for (int j = 0; j < d; ++j) {
                 u[j] = lo[j] + t[j] * h[j];
                 double wt = (t[j] == 0 || t[j] == n[j] - 1) ? 0.5 : 1.0;
@@ -251,7 +254,7 @@ int oracle_bounds(int d, double gamma, double r_fac, double rho_floor,
                   const int* rowptr, const int* cols,
                   const int64_t* elems, int64_t n_sel, int energy_mode,
                   double* bounds, unsigned* status) {
-    if (d < 1 || d > 2 || n_s < 1 || !(gamma > 1.0)) return -1;
+    if (d < 1 || d > 3 || n_s < 1 || !(gamma > 1.0)) return -1;
     if (energy_mode != 0 && energy_mode != 1) return -1;
     for (int j = 0; j < d; ++j) if (n[j] < 2) return -1;
     if (oracle_delta(d, gamma) < 0.0) return -1;
@@ -369,7 +372,7 @@ int oracle_limit(int d, double gamma, double p_floor, double eps,
                  const double* bounds, const double* c, int independent,
                  const int64_t* elems, int64_t n_sel,
                  double* limited, double* alpha, unsigned* status) {
-    if (d < 1 || d > 2 || n_s < 1 || n_s > 4096 || !(gamma > 1.0)) return -1;
+    if (d < 1 || d > 3 || n_s < 1 || n_s > 4096 || !(gamma > 1.0)) return -1;
     double csum = 0.0;
     for (int j = 0; j < n_s; ++j) {
         if (!(c[j] >= 0.0) || !isfinite(c[j])) return -1;
@@ -761,11 +764,11 @@ int oracle_riemann(int d, double gamma, int64_t n_pairs, int64_t n_nodes, const 
                    const int* ni, const int* nj, const double* normals, const double* lam,
                    const double* bounds, const int* elem, int64_t n_elem,
                    double* bar, unsigned* status) {
-    if (d < 1 || d > 2 || !(gamma > 1.0)) return -1;
+    if (d < 1 || d > 3 || !(gamma > 1.0)) return -1;
     const int nv = d + 2;
 #pragma omp parallel for schedule(static)
     for (int64_t q = 0; q < n_pairs; ++q) {
-        double wi[OR_MAXV], wj[OR_MAXV], fi[OR_MAXV], fj[OR_MAXV], n[2] = {0, 0};
+        double wi[OR_MAXV], wj[OR_MAXV], fi[OR_MAXV], fj[OR_MAXV], n[3] = {0, 0, 0};
         unsigned st = 0;
         const int64_t a = ni[q], b = nj[q];
         int ok = a >= 0 && a < n_nodes && b >= 0 && b < n_nodes;

@@ -14,6 +14,7 @@ from .workloads import (  # noqa: F401
     make_quad_workload,
     make_tri_workload,
     make_quad_fr_workload,
+    make_hex_workload,
     NodeWorkload,
     sample_elements,
     WORKLOADS,

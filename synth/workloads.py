@@ -331,6 +331,67 @@ def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int 
 
 
 # ----------------------------------------------------------------------------
+# 3D periodic hexahedra, tensor Gauss-Legendre nodes, self + 6 face neighbours.
+# ----------------------------------------------------------------------------
+
+def _fourier3(rng: np.random.Generator, x, y, z, n_modes: int = 8) -> np.ndarray:
+    """Smooth periodic 3D perturbation with unit max amplitude bound."""
+    out = np.zeros_like(x)
+    amps = rng.uniform(0.5, 1.0, n_modes)
+    k = rng.integers(-3, 4, (n_modes, 3))
+    ph = rng.uniform(0.0, 2 * np.pi, n_modes)
+    for a, (i, j, l), f in zip(amps, k, ph):
+        out += a * np.sin(2 * np.pi * (i * x + j * y + l * z) + f)
+    return out / amps.sum()
+
+
+def make_hex_workload(N: int = 32, p: int = 2, seed: int = BASE_SEED + 6,
+                      grid_nodes: int = 24, k: float = 4.0, gamma: float = 1.4,
+                      r_fac: float = 1e-3, name: str = "hex") -> Workload:
+    """3D Euler on periodic N^3 hexahedra, p = 2 (27 Gauss-Legendre nodes per
+    element), face stencils of 7 elements (189 states), an eight-octant
+    Riemann field (rho ~ logU[0.1, 10], p ~ logU[0.1, 100], |U| <= 3) with a
+    1% smooth perturbation, per-stencil velocity box (k = 4) of grid_nodes^3."""
+    rng = _rng(seed)
+    n1 = p + 1
+    n_s = n1 ** 3
+    xi, wq = np.polynomial.legendre.leggauss(n1)
+    n_elem = N ** 3
+    ez, rem = np.divmod(np.arange(n_elem), N * N)
+    ey, ex = np.divmod(rem, N)
+    t = 0.5 * (xi + 1.0)
+    # node j = (jz*n1 + jy)*n1 + jx
+    jz, jr = np.divmod(np.arange(n_s), n1 * n1)
+    jy, jx = np.divmod(jr, n1)
+    X = (ex[:, None] + t[jx][None, :]) / N
+    Y = (ey[:, None] + t[jy][None, :]) / N
+    Z = (ez[:, None] + t[jz][None, :]) / N
+    off = rng.uniform(0.2, 0.8, 3)
+    cut = (N // 2 + off) / N
+    octant = ((X >= cut[0]).astype(np.int64) + 2 * (Y >= cut[1]).astype(np.int64)
+              + 4 * (Z >= cut[2]).astype(np.int64))
+    rho_o = np.exp(rng.uniform(np.log(0.1), np.log(10.0), 8))
+    p_o = np.exp(rng.uniform(np.log(0.1), np.log(100.0), 8))
+    r_o = rng.uniform(0.0, 3.0, 8)
+    d = rng.standard_normal((8, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    rho = rho_o[octant] * (1.0 + 0.01 * _fourier3(rng, X, Y, Z))
+    pr = p_o[octant] * (1.0 + 0.01 * _fourier3(rng, X, Y, Z))
+    vel = [(r_o[:, None] * d)[:, c][octant] + 0.03 * _fourier3(rng, X, Y, Z) for c in range(3)]
+    states = _to_conserved(gamma, rho, vel, pr)
+    own = np.arange(n_elem)
+    nb = lambda dx, dy, dz: ((ez + dz) % N) * N * N + ((ey + dy) % N) * N + (ex + dx) % N
+    cols = np.stack([own, nb(-1, 0, 0), nb(1, 0, 0), nb(0, -1, 0), nb(0, 1, 0), nb(0, 0, -1),
+                     nb(0, 0, 1)], 1).ravel().astype(np.int32)
+    rowptr = np.arange(0, 7 * n_elem + 1, 7).astype(np.int32)
+    w3 = (wq[jz] * wq[jy] * wq[jx]).astype(np.float64)
+    grid = GridSpec(GRID_STENCIL, (grid_nodes,) * 3, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), k)
+    target, jumpy = _limit_target(rng, states, rowptr, cols, n_s, w3)
+    return Workload(name, 3, gamma, n_elem, n_s, states, target, rowptr, cols, w3, grid, r_fac,
+                    seed, {"jump_elems": np.nonzero(jumpy)[0], "N": N})
+
+
+# ----------------------------------------------------------------------------
 # 2D quads with the node-level stencil of an FR scheme: solution points plus
 # flux points on the faces (the stencil the paper runs, Sec. 5).
 # ----------------------------------------------------------------------------
@@ -547,6 +608,9 @@ WORKLOADS: Dict[str, Callable[..., Workload]] = {
     # 512^2 quads, p=3, 48x48 per-stencil grid, used for the backward
     "quad512": lambda **kw: make_quad_workload(**{"N": 512, "seed": BASE_SEED + 4,
                                                   "grid_nodes": 48, "name": "quad512", **kw}),
+    # 32^3 hexahedra, p=2, 189-state face stencils, 24^3 per-stencil velocity grid
+    "hex32": lambda **kw: make_hex_workload(**{"N": 32, "seed": BASE_SEED + 6, "grid_nodes": 24,
+                                               "name": "hex32", **kw}),
     # 256^2 quads, p=3, node-level stencils of solution + flux points (48 states)
     "quad256_fr": lambda **kw: make_quad_fr_workload(**{"N": 256, "seed": BASE_SEED + 5,
                                                         "grid_nodes": 48, "name": "quad256_fr",
