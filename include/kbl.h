@@ -26,8 +26,12 @@
  *  - Conserved states are stored SoA: row v of a [d+2][n_elem*n_s] array
  *    holds variable v (rho, m_1..m_d, E) of every node; the nodes of element e
  *    are e*n_s .. e*n_s+n_s-1.
- *  - Spatial dimension d is 1 or 2.  gamma > 1 and delta = 2/(gamma-1) - d
- *    must be >= 0 (Sec. 3.6).
+ *  - Spatial dimension d is 1, 2 or 3.  gamma > 1 and delta = 2/(gamma-1) - d
+ *    must be >= 0 (Sec. 3.6).  d = 3 (the extension the paper's conclusion
+ *    names as costly, Sec. 7) is built for the FP64 bounds with the default
+ *    energy model, the limiter and the Riemann-averaged states; the mixed
+ *    precisions, KBL_FLAG_ENERGY_PERSTATE and the backward return
+ *    KBL_ERR_UNSUPPORTED for it.
  *  - No exception crosses this interface.
  */
 #ifndef KBL_H
@@ -70,15 +74,16 @@ typedef enum {
 #define KBL_ST_PMEAN_FLOOR   0x20u   /* P(mean) <= p_floor: alpha_P = 0 (element flattened) */
 #define KBL_ST_MEAN_OUTSIDE  0x40u   /* element mean lies outside its bounds */
 #define KBL_ST_BAD_BOUNDS    0x80u   /* bounds not finite: element passed through unchanged */
-#define KBL_ST_BAD_STENCIL   0x100u  /* stencil row out of range (rowptr or cols): bounds are NaN */
+#define KBL_ST_BAD_STENCIL   0x100u  /* stencil row out of range (rowptr or cols): bounds are NaN; set alone */
 #define KBL_ST_TOO_LARGE     0x200u  /* mixed precision and backward: more than 256 stencil states (NaN bounds / zero gradient) */
 #define KBL_ST_ASYMMETRIC    0x400u  /* backward: a stencil neighbour does not list this element back */
 
 typedef struct {
     int32_t mode;       /* KBL_GRID_GLOBAL or KBL_GRID_STENCIL */
-    int32_t n[2];       /* nodes per direction, endpoints included (n[1] ignored for d = 1) */
-    double  lo[2];      /* GLOBAL: lower box corner */
-    double  hi[2];      /* GLOBAL: upper box corner */
+    int32_t n[3];       /* nodes per direction, endpoints included (entries >= d ignored);
+                           at most 4096 (d = 1; 2048 for the backward) or 64 per direction (d = 2, 3) */
+    double  lo[3];      /* GLOBAL: lower box corner */
+    double  hi[3];      /* GLOBAL: upper box corner */
     double  k;          /* STENCIL: extent in thermal units (the paper uses 4 in 2D, 8 in 1D) */
 } kbl_vgrid;
 
@@ -161,8 +166,9 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
 /*
  * Tuning knobs read from the environment at each kbl_compute_bounds call
  * (meant for measurements and tests; they override kbl_autotune_bounds):
- *   KBL_BOUNDS_TILE=<t>        FP64 2D tile configuration index (ignored if
- *                              it does not cover the velocity grid)
+ *   KBL_BOUNDS_TILE=<t>        FP64 tile configuration index of the 2D or 3D
+ *                              kernel (ignored if it does not cover the
+ *                              velocity grid)
  *   KBL_MIXED_TILE=<t>         mixed-precision tile configuration index
  *   KBL_PERSISTENT_BLOCKS=<g>  grid of g workgroups walking the elements
  *                              (0 = one workgroup per element)
@@ -294,8 +300,8 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
  *   workspace    device memory of at least kbl_backward_workspace_bytes().
  * Element-level stencils and params->flags == 0 only (KBL_ERR_UNSUPPORTED
  * otherwise).  Stencils of more than 256 states contribute no state gradient
- * (KBL_ST_TOO_LARGE).  Grids: up to 64 x 64 (d = 2), 2048 nodes (d = 1).
- * The result is bitwise deterministic.
+ * (KBL_ST_TOO_LARGE).  Grids: up to 64 x 64 (d = 2), 2048 nodes (d = 1);
+ * d = 3 is not built.  The result is bitwise deterministic.
  */
 kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
                                      int32_t n_s, int64_t nnz, const double* states,

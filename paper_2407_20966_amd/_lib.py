@@ -33,6 +33,10 @@ FP64_TILES = {0: (16, 16, 1, 1, 0), 1: (16, 16, 2, 2, 0), 2: (16, 16, 3, 3, 0),
               6: (16, 16, 4, 4, 1), 7: (32, 8, 2, 8, 1), 8: (16, 16, 2, 4, 0),
               9: (16, 16, 4, 2, 0), 10: (16, 16, 2, 2, 2), 11: (16, 16, 3, 3, 2),
               12: (16, 16, 4, 4, 2), 13: (16, 8, 3, 6, 2)}
+# d = 3 tiles: (BX, BY, BZ, TX, TY, TZ) covers nx <= BX TX, ny <= BY TY, any nz
+FP64_TILES_3D = {0: (8, 8, 4, 2, 2, 2), 1: (8, 8, 4, 3, 3, 1), 2: (16, 16, 1, 2, 2, 2),
+                 3: (16, 16, 1, 3, 3, 1), 4: (16, 16, 1, 4, 4, 1), 5: (8, 8, 4, 2, 2, 4),
+                 6: (8, 8, 4, 3, 3, 2), 7: (8, 8, 4, 4, 4, 1), 8: (16, 16, 1, 3, 3, 2)}
 MIXED_TILES = {0: (1, 1, 1), 1: (2, 2, 1), 2: (1, 2, 2), 3: (3, 3, 1), 4: (1, 3, 3),
                5: (2, 4, 2), 6: (1, 4, 4)}
 RS_BAD_INPUT = 1 << 16
@@ -53,8 +57,8 @@ ST_ASYMMETRIC = 0x400
 
 
 class VGrid(C.Structure):
-    _fields_ = [("mode", C.c_int32), ("n", C.c_int32 * 2), ("lo", C.c_double * 2),
-                ("hi", C.c_double * 2), ("k", C.c_double)]
+    _fields_ = [("mode", C.c_int32), ("n", C.c_int32 * 3), ("lo", C.c_double * 3),
+                ("hi", C.c_double * 3), ("k", C.c_double)]
 
 
 class Params(C.Structure):

@@ -45,6 +45,7 @@ def hipcc() -> str:
 # min/max need no canonicalisation (one VALU op per min/max, not two).
 SOURCE_FLAGS = {
     "bounds_fp64.hip": ["-fno-honor-nans"],
+    "bounds_fp64_3d.hip": ["-fno-honor-nans"],
     "bounds_mixed.hip": ["-fno-honor-nans"],
     "backward_fp64.hip": ["-fno-honor-nans"],
 }

@@ -14,6 +14,7 @@
 namespace {
 
 constexpr int kMax2DNodesPerDim = 64;
+constexpr int kMax3DNodesPerDim = 64;
 constexpr int kMax1DNodes = 4096;
 constexpr int kMax1DBackwardNodes = 2048;
 
@@ -28,7 +29,7 @@ bool internal_dof(int dim, double gamma, double* half_delta) {
 constexpr int32_t kKnownFlags = KBL_FLAG_INDEPENDENT_ALPHA | KBL_FLAG_ENERGY_PERSTATE;
 
 kbl_status check_params(const kbl_params* p, int32_t dim, double* half_delta) {
-    if (!p || (dim != 1 && dim != 2) || (p->flags & ~kKnownFlags) != 0) return KBL_ERR_ARG;
+    if (!p || dim < 1 || dim > 3 || (p->flags & ~kKnownFlags) != 0) return KBL_ERR_ARG;
     if (!(p->gamma > 1.0) || !isfinite(p->gamma)) return KBL_ERR_GAMMA;
     if (!internal_dof(dim, p->gamma, half_delta)) return KBL_ERR_GAMMA;
     if (!(p->r_fac >= 0.0 && p->r_fac < 1.0)) return KBL_ERR_ARG;
@@ -54,7 +55,8 @@ kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_ele
     if (g.mode != KBL_GRID_GLOBAL && g.mode != KBL_GRID_STENCIL) return KBL_ERR_GRID;
     for (int j = 0; j < dim; ++j) {
         if (g.n[j] < 2) return KBL_ERR_GRID;
-        if (g.n[j] > (dim == 2 ? kMax2DNodesPerDim : max1d)) return KBL_ERR_GRID;
+        if (g.n[j] > (dim == 3 ? kMax3DNodesPerDim : dim == 2 ? kMax2DNodesPerDim : max1d))
+            return KBL_ERR_GRID;
         if (g.mode == KBL_GRID_GLOBAL &&
             !(isfinite(g.lo[j]) && isfinite(g.hi[j]) && g.hi[j] > g.lo[j]))
             return KBL_ERR_GRID;
@@ -72,11 +74,14 @@ kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_ele
     a->grid_mode = g.mode;
     a->energy_perstate = (params->flags & KBL_FLAG_ENERGY_PERSTATE) ? 1 : 0;
     a->nx = g.n[0];
-    a->ny = dim == 2 ? g.n[1] : 1;
+    a->ny = dim >= 2 ? g.n[1] : 1;
+    a->nz = dim == 3 ? g.n[2] : 1;
     a->lo0 = g.lo[0];
     a->hi0 = g.hi[0];
-    a->lo1 = dim == 2 ? g.lo[1] : 0.0;
-    a->hi1 = dim == 2 ? g.hi[1] : 0.0;
+    a->lo1 = dim >= 2 ? g.lo[1] : 0.0;
+    a->hi1 = dim >= 2 ? g.hi[1] : 0.0;
+    a->lo2 = dim == 3 ? g.lo[2] : 0.0;
+    a->hi2 = dim == 3 ? g.hi[2] : 0.0;
     a->k = g.k;
     a->gm1 = params->gamma - 1.0;
     a->half_delta = half_delta;
@@ -117,9 +122,10 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 // ---------------------------------------------------------------- autotune
 // Launch choices found by kbl_autotune_bounds, per problem shape.
 struct TuneKey {
-    int dim, prec, nx, ny, n_s, mode;
+    int dim, prec, nx, ny, nz, n_s, mode;
     bool operator<(const TuneKey& o) const {
-        return std::tie(dim, prec, nx, ny, n_s, mode) < std::tie(o.dim, o.prec, o.nx, o.ny, o.n_s, o.mode);
+        return std::tie(dim, prec, nx, ny, nz, n_s, mode) <
+               std::tie(o.dim, o.prec, o.nx, o.ny, o.nz, o.n_s, o.mode);
     }
 };
 struct TuneVal {
@@ -130,7 +136,7 @@ std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
 
 TuneKey tune_key(const kbl::BoundsArgs& a, int dim, int prec) {
-    return TuneKey{dim, prec, a.nx, a.ny, a.n_s, a.grid_mode};
+    return TuneKey{dim, prec, a.nx, a.ny, a.nz, a.n_s, a.grid_mode};
 }
 
 bool tuned(const TuneKey& k, TuneVal* v) {
@@ -142,8 +148,17 @@ bool tuned(const TuneKey& k, TuneVal* v) {
 }
 
 hipError_t launch_bounds_any(const kbl::BoundsArgs& a, int dim, int prec, int tile, hipStream_t st) {
+    if (dim == 3) return kbl::launch_bounds_fp64_3d(a, st, tile);
     return prec == KBL_PREC_FP64 ? kbl::launch_bounds_fp64(a, dim, st, tile)
                                  : kbl::launch_bounds_mixed(a, prec, st, tile);
+}
+
+// Whether a tile index names a launch configuration that covers the grid.
+bool tile_fits(const kbl::BoundsArgs& a, int dim, int prec, int tile) {
+    if (dim == 3) return kbl::bounds_tile_fits_3d(tile, a.nx, a.ny, a.nz);
+    if (dim != 2) return false;
+    return prec == KBL_PREC_FP64 ? kbl::bounds_tile_fits_2d(tile, a.nx, a.ny)
+                                 : kbl::mixed_tile_fits_2d(tile, a.nx, a.ny);
 }
 
 
@@ -164,6 +179,7 @@ kbl_status compute_bounds_impl(const kbl_params* params, int32_t dim, int64_t n_
         prec != KBL_PREC_MIXED_FP32)
         return KBL_ERR_UNSUPPORTED;
     if (prec != KBL_PREC_FP64 && (dim != 2 || a.energy_perstate)) return KBL_ERR_UNSUPPORTED;
+    if (dim == 3 && a.energy_perstate) return KBL_ERR_UNSUPPORTED;
     a.bounds = bounds;
     a.status = elem_status;
     if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
@@ -181,7 +197,7 @@ kbl_status compute_bounds_impl(const kbl_params* params, int32_t dim, int64_t n_
     if (const char* env = getenv(prec == KBL_PREC_FP64 ? "KBL_BOUNDS_TILE" : "KBL_MIXED_TILE"))
         tile = atoi(env);
     if (const char* env = getenv("KBL_PERSISTENT_BLOCKS")) a.grid_blocks = atoll(env);
-    if (prec == KBL_PREC_FP64 && dim == 2 && !kbl::bounds_tile_fits_2d(tile, a.nx, a.ny)) tile = -1;
+    if (prec == KBL_PREC_FP64 && dim >= 2 && !tile_fits(a, dim, prec, tile)) tile = -1;
     const hipError_t err = launch_bounds_any(a, dim, prec, tile, (hipStream_t)stream);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
@@ -201,7 +217,7 @@ void kbl_default_params(kbl_params* p, double gamma) {
     p->precision = KBL_PREC_FP64;
 }
 
-int32_t kbl_version(void) { return 100; }
+int32_t kbl_version(void) { return 110; }
 
 const char* kbl_status_string(kbl_status s) {
     switch (s) {
@@ -251,12 +267,11 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
     // candidates: every tile that fits the grid x {one workgroup per element,
     // persistent grids of 1, 2, 4, 8 workgroups per CU}
     std::vector<int> tiles;
-    if (dim == 2) {
-        const int nt = prec == KBL_PREC_FP64 ? kbl::bounds_tile_count_2d() : kbl::mixed_tile_count();
+    if (dim >= 2) {
+        const int nt = dim == 3 ? kbl::bounds_tile_count_3d()
+                       : prec == KBL_PREC_FP64 ? kbl::bounds_tile_count_2d() : kbl::mixed_tile_count();
         for (int t = 0; t < nt; ++t)
-            if (prec == KBL_PREC_FP64 ? kbl::bounds_tile_fits_2d(t, a.nx, a.ny)
-                                      : kbl::mixed_tile_fits_2d(t, a.nx, a.ny))
-                tiles.push_back(t);
+            if (tile_fits(a, dim, prec, t)) tiles.push_back(t);
     } else {
         tiles.push_back(-1);
     }
@@ -290,9 +305,10 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
         *ms_out = best_trial;
         return true;
     };
-    const int def_tile = dim == 2 ? (prec == KBL_PREC_FP64 ? kbl::bounds_default_tile_2d(a.nx, a.ny)
-                                                          : kbl::mixed_default_tile_2d(a.nx, a.ny, prec))
-                                  : -1;
+    const int def_tile = dim == 3   ? kbl::bounds_default_tile_3d(a.nx, a.ny, a.nz)
+                         : dim == 2 ? (prec == KBL_PREC_FP64 ? kbl::bounds_default_tile_2d(a.nx, a.ny)
+                                                             : kbl::mixed_default_tile_2d(a.nx, a.ny, prec))
+                                    : -1;
     float best = 1e30f;
     TuneVal bestv{-1, 0};
     int best_idx = -1;
@@ -400,6 +416,7 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     kbl_status rc = make_bounds_args(params, dim, n_elem, n_elem, n_s, nnz, states, rowptr, cols,
                                      vgrid, kMax1DBackwardNodes, &fa);
     if (rc != KBL_OK) return rc;
+    if (dim == 3) return KBL_ERR_UNSUPPORTED;   // backward built for d = 1, 2
     kbl::LimitArgs la;
     rc = make_limit_args(params, dim, n_elem, n_s, node_weights, &la);
     if (rc != KBL_OK) return rc;

@@ -20,7 +20,7 @@ constexpr double kInf = __builtin_inf();
 constexpr float kInfF = __builtin_inff();
 
 struct Prim {
-    double rho, ux, uy, th;
+    double rho, ux, uy, uz, th;
     bool ok;
 };
 
@@ -33,23 +33,28 @@ __device__ __forceinline__ bool finite_bits(double x) {
 
 template <int D>
 __device__ __forceinline__ Prim load_prim(const BoundsArgs& p, int64_t node) {
+    static_assert(D >= 1 && D <= 3, "d = 1, 2 or 3");
     Prim s;
     const double rho = p.states[node];
     const double mx = p.states[p.n_nodes + node];
-    const double my = (D == 2) ? p.states[2 * p.n_nodes + node] : 0.0;
+    const double my = (D >= 2) ? p.states[2 * p.n_nodes + node] : 0.0;
+    const double mz = (D == 3) ? p.states[3 * p.n_nodes + node] : 0.0;
     const double E = p.states[(D + 1) * p.n_nodes + node];
     double mm, P;
     {
 #pragma clang fp contract(off)
-        mm = (D == 2) ? mx * mx + my * my : mx * mx;
+        mm = mx * mx;
+        if (D >= 2) mm = mm + my * my;
+        if (D == 3) mm = mm + mz * mz;
         P = p.gm1 * (E - 0.5 * mm / rho);
     }
     s.rho = rho;
     s.ux = mx / rho;
-    s.uy = (D == 2) ? my / rho : 0.0;
+    s.uy = (D >= 2) ? my / rho : 0.0;
+    s.uz = (D == 3) ? mz / rho : 0.0;
     s.th = P / rho;
-    s.ok = finite_bits(rho) && finite_bits(mx) && finite_bits(my) && finite_bits(E) &&
-           finite_bits(P) && finite_bits(s.th) && rho > 0.0 && P > 0.0;
+    s.ok = finite_bits(rho) && finite_bits(mx) && finite_bits(my) && finite_bits(mz) &&
+           finite_bits(E) && finite_bits(P) && finite_bits(s.th) && rho > 0.0 && P > 0.0;
     return s;
 }
 
@@ -160,6 +165,13 @@ struct Coef {
     double ux, uy;
     double nk;   // -1 / (2 theta)
 };
+// The same for d = 3 (kept apart so that the LDS staging of the d <= 2
+// kernels does not grow).
+struct Coef3 {
+    double a, al;
+    double ux, uy, uz;
+    double nk;
+};
 
 // FP32 coefficients of the mixed-precision forms: shifted by the element's
 // log-peak references and centred on the velocity box.
@@ -171,13 +183,14 @@ struct CoefF {
     float nk;   // -1 / (2 theta)
 };
 
-template <int D>
-__device__ __forceinline__ Coef make_coef(const BoundsArgs& p, const Prim& s) {
-    Coef c;
+template <int D, class CT = Coef>
+__device__ __forceinline__ CT make_coef(const BoundsArgs& p, const Prim& s) {
+    CT c;
     c.a = log(s.rho) - (0.5 * D) * log(2.0 * kPi * s.th);
     c.al = (p.half_delta > 0.0) ? c.a + log(s.th * p.half_delta) : -kInf;
     c.ux = s.ux;
     c.uy = s.uy;
+    if constexpr (D == 3) c.uz = s.uz;
     c.nk = -0.5 / s.th;
     return c;
 }
@@ -190,23 +203,25 @@ __device__ __forceinline__ int64_t state_node(const BoundsArgs& p, int64_t row0,
 
 // Prologue: admissibility, velocity box, and (if sC is given) the
 // coefficients of the first kMaxStates states staged in sC.  Returns status
-// bits (uniform).
+// bits (uniform).  box: (lo, hi) per direction, box[2j] and box[2j+1] for
+// j < D.
 // ref (optional): max over the stencil of a and of a + l, the log-peak
 // references the mixed-precision kernels shift by.
-template <int D, int NT>
+template <int D, int NT, class CT>
 __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t S, Red& red,
-                                     Coef* sC, double box[4], double* ref = nullptr) {
+                                     CT* sC, double box[2 * D], double* ref = nullptr) {
     constexpr int NW = NT / 64;
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     uint32_t bad = 0;
-    double lx = kInf, hx = -kInf, ly = kInf, hy = -kInf, ra = -kInf, rl = -kInf;
+    double lx = kInf, hx = -kInf, ly = kInf, hy = -kInf, lz = kInf, hz = -kInf;
+    double ra = -kInf, rl = -kInf;
     for (int64_t s = tid; s < S; s += NT) {
         const int32_t col = p.cols[row0 + s / p.n_s];
         if (col < 0 || col >= p.n_src) { bad |= KBL_ST_BAD_STENCIL; continue; }
         const Prim st = load_prim<D>(p, (int64_t)col * p.n_s + s % p.n_s);
         if (!st.ok) { bad |= KBL_ST_INADMISSIBLE; continue; }
-        const Coef c = make_coef<D>(p, st);
+        const CT c = make_coef<D, CT>(p, st);
         if (sC && s < kMaxStates) sC[s] = c;
         ra = fmax(ra, c.a);
         rl = fmax(rl, c.al);
@@ -214,51 +229,65 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t 
             const double sd = sqrt(st.th);
             lx = fmin(lx, box_lo(st.ux, p.k, sd));
             hx = fmax(hx, box_hi(st.ux, p.k, sd));
-            if (D == 2) {
+            if (D >= 2) {
                 ly = fmin(ly, box_lo(st.uy, p.k, sd));
                 hy = fmax(hy, box_hi(st.uy, p.k, sd));
+            }
+            if (D == 3) {
+                lz = fmin(lz, box_lo(st.uz, p.k, sd));
+                hz = fmax(hz, box_hi(st.uz, p.k, sd));
             }
         }
     }
     if (tid == 0) red.flags = 0;
-    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    lx = wave_min(lx); hx = wave_max(hx);
+    if (D >= 2) { ly = wave_min(ly); hy = wave_max(hy); }
+    if (D == 3) { lz = wave_min(lz); hz = wave_max(hz); }
     if (ref) { ra = wave_max(ra); rl = wave_max(rl); }
     __syncthreads();
     if (bad) atomicOr(&red.flags, bad);
     if (lane == 0) {
         red.v[wid][0] = lx; red.v[wid][1] = hx; red.v[wid][2] = ly; red.v[wid][3] = hy;
-        red.v[wid][4] = ra; red.v[wid][5] = rl;
+        red.v[wid][4] = lz; red.v[wid][5] = hz;
+        red.v[wid][6] = ra; red.v[wid][7] = rl;
     }
     __syncthreads();
     if (ref) {
-        ref[0] = red.v[0][4];
-        ref[1] = red.v[0][5];
+        ref[0] = red.v[0][6];
+        ref[1] = red.v[0][7];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) { ref[0] = fmax(ref[0], red.v[w][4]); ref[1] = fmax(ref[1], red.v[w][5]); }
+        for (int w = 1; w < NW; ++w) { ref[0] = fmax(ref[0], red.v[w][6]); ref[1] = fmax(ref[1], red.v[w][7]); }
     }
     if (p.grid_mode == KBL_GRID_STENCIL) {
-        box[0] = red.v[0][0]; box[1] = red.v[0][1]; box[2] = red.v[0][2]; box[3] = red.v[0][3];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) {
-            box[0] = fmin(box[0], red.v[w][0]); box[1] = fmax(box[1], red.v[w][1]);
-            box[2] = fmin(box[2], red.v[w][2]); box[3] = fmax(box[3], red.v[w][3]);
-        }
+        for (int j = 0; j < 2 * D; ++j) box[j] = red.v[0][j];
+#pragma unroll
+        for (int w = 1; w < NW; ++w)
+#pragma unroll
+            for (int j = 0; j < D; ++j) {
+                box[2 * j] = fmin(box[2 * j], red.v[w][2 * j]);
+                box[2 * j + 1] = fmax(box[2 * j + 1], red.v[w][2 * j + 1]);
+            }
     } else {
-        box[0] = p.lo0; box[1] = p.hi0; box[2] = p.lo1; box[3] = p.hi1;
+        const double glo[3] = {p.lo0, p.lo1, p.lo2}, ghi[3] = {p.hi0, p.hi1, p.hi2};
+#pragma unroll
+        for (int j = 0; j < D; ++j) { box[2 * j] = glo[j]; box[2 * j + 1] = ghi[j]; }
     }
-    const uint32_t flags = red.flags;
+    uint32_t flags = red.flags;
+    // a bad row is reported alone (its other states are not a stencil)
+    if (flags & KBL_ST_BAD_STENCIL) flags = KBL_ST_BAD_STENCIL;
     __syncthreads();   // red is reused by the caller
     return flags;
 }
 
 // Stage the coefficients of states [c0, c0 + cn) into sC (chunks after the
 // first, for stencils larger than kMaxStates).  Bracketed by barriers.
-template <int D, int NT>
+template <int D, int NT, class CT>
 __device__ __forceinline__ void stage_chunk(const BoundsArgs& p, int64_t row0, int64_t c0, int cn,
-                                            Coef* sC) {
+                                            CT* sC) {
     __syncthreads();
     for (int s = threadIdx.x; s < cn; s += NT)
-        sC[s] = make_coef<D>(p, load_prim<D>(p, state_node(p, row0, c0 + s)));
+        sC[s] = make_coef<D, CT>(p, load_prim<D>(p, state_node(p, row0, c0 + s)));
     __syncthreads();
 }
 

@@ -1,0 +1,263 @@
+// FP64 kinetic bounds over a three-dimensional velocity grid (d = 3), gfx950.
+//
+// Same three steps as the 2D kernel (overview of Sec. 3.9): prologue with the
+// admissibility checks and the velocity box of eq. truncdomain, the min/max
+// envelopes of eq. fminmax in the log domain, then relaxation (eq. relaxed),
+// trapezoid weights (Sec. 3.7) and the moments (eq. rhobounds, Ebounds,
+// mmbounds, mpbounds) with the internal part of Sec. 3.6.
+//
+// The log-Maxwellian separates over the three velocity directions,
+//   q_i(u) = A_i[jx] + B_i[jy] + C_i[jz],
+// with A_i carrying ln rho_i - (3/2) ln(2 pi theta_i).  The internal part is
+// q_i + l_i with l_i = ln(theta_i delta / 2), a per-state constant.  The
+// velocity grid is walked in z-slabs (passes): the four running extrema of a
+// slab's nodes stay in registers, and per (state, node) pair the hot loop
+// spends one add for q, one for q + l and four min/max.  Per state a thread
+// reads its A, B, C values from LDS tables (built per chunk of states and per
+// slab) and forms B + C for its (y, z) nodes once, reused over its x nodes.
+// Each slab is contracted (four exp per node) before the next one starts.
+//
+// Threads: BX x BY x BZ, thread (tx, ty, tz) owns nodes (tx + BX i,
+// ty + BY j, z0 + tz + BZ k) of slab z0, i < TX, j < TY, k < TZ.  Inputs are
+// validated before the hot loop, which therefore sees no NaN (only finite
+// values and -inf when delta = 0); this unit is built with -fno-honor-nans.
+#include "bounds_common.h"
+
+namespace kbl {
+namespace {
+
+template <int BX, int BY, int BZ, int TX, int TY, int TZ>
+__global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
+    constexpr int NT = BX * BY * BZ;
+    constexpr int NXM = BX * TX;   // x nodes covered
+    constexpr int NYM = BY * TY;   // y nodes covered
+    constexpr int NZP = BZ * TZ;   // z nodes per slab
+    constexpr int kTab = 32;       // states per table chunk
+    static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    __shared__ Coef3 sC[kMaxStates];
+    __shared__ double sA[kTab][NXM];
+    __shared__ double sB[kTab][NYM];
+    __shared__ double sZ[kTab][NZP];
+    __shared__ double sL[kTab];
+    __shared__ double sTot[10];    // moment sums of the finished slabs (thread 0)
+    __shared__ Red red;
+
+    const int tid = threadIdx.x;
+    const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
+    const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+
+    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+        const int64_t e = er.e;
+        const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
+        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
+            if (tid == 0) store_nan<3>(p, e, KBL_ST_BAD_STENCIL);
+            continue;
+        }
+        const int64_t S = (row1 - row0) * p.n_s;
+        double box[6];
+        const uint32_t flags = stencil_prologue<3, NT>(p, row0, S, red, sC, box);
+        if (flags & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE)) {
+            if (tid == 0) store_nan<3>(p, e, flags);
+            continue;
+        }
+        const double lox = box[0], loy = box[2], loz = box[4];
+        const double hx = (box[1] - box[0]) / (double)(p.nx - 1);
+        const double hy = (box[3] - box[2]) / (double)(p.ny - 1);
+        const double hz = (box[5] - box[4]) / (double)(p.nz - 1);
+
+        for (int z0 = 0; z0 < p.nz; z0 += NZP) {
+            double qtn[TX][TY][TZ], qtx[TX][TY][TZ], qin[TX][TY][TZ], qix[TX][TY][TZ];
+#pragma unroll
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j)
+#pragma unroll
+                    for (int k = 0; k < TZ; ++k) {
+                        qtn[i][j][k] = kInf; qtx[i][j][k] = -kInf;
+                        qin[i][j][k] = kInf; qix[i][j][k] = -kInf;
+                    }
+
+            for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
+                const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
+                // sC holds the first chunk after the prologue; later chunks,
+                // and the first one again on later slabs, are restaged
+                if (c0 > 0 || (z0 > 0 && S > kMaxStates)) stage_chunk<3, NT>(p, row0, c0, cn, sC);
+                for (int t0 = 0; t0 < cn; t0 += kTab) {
+                    const int tn = (cn - t0) < kTab ? (cn - t0) : kTab;
+                    __syncthreads();
+                    for (int idx = tid; idx < tn * NXM; idx += NT) {
+                        const int s = idx / NXM, i = idx - s * NXM;
+                        const int ic = i < p.nx ? i : p.nx - 1;
+                        const Coef3& c = sC[t0 + s];
+                        const double d = node_pos(lox, ic, hx) - c.ux;
+                        sA[s][i] = fma(c.nk * d, d, c.a);
+                    }
+                    for (int idx = tid; idx < tn * NYM; idx += NT) {
+                        const int s = idx / NYM, j = idx - s * NYM;
+                        const int jc = j < p.ny ? j : p.ny - 1;
+                        const Coef3& c = sC[t0 + s];
+                        const double d = node_pos(loy, jc, hy) - c.uy;
+                        sB[s][j] = (c.nk * d) * d;
+                    }
+                    for (int idx = tid; idx < tn * NZP; idx += NT) {
+                        const int s = idx / NZP, k = idx - s * NZP;
+                        const int jz = z0 + k < p.nz ? z0 + k : p.nz - 1;
+                        const Coef3& c = sC[t0 + s];
+                        const double d = node_pos(loz, jz, hz) - c.uz;
+                        sZ[s][k] = (c.nk * d) * d;
+                    }
+                    for (int s = tid; s < tn; s += NT) sL[s] = sC[t0 + s].al - sC[t0 + s].a;
+                    __syncthreads();
+#pragma unroll 2
+                    for (int s = 0; s < tn; ++s) {
+                        double a[TX], zc[TZ], bc[TY][TZ];
+                        const double l = sL[s];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) a[i] = sA[s][tx + BX * i];
+#pragma unroll
+                        for (int k = 0; k < TZ; ++k) zc[k] = sZ[s][tz + BZ * k];
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            const double b = sB[s][ty + BY * j];
+#pragma unroll
+                            for (int k = 0; k < TZ; ++k) bc[j][k] = b + zc[k];
+                        }
+#pragma unroll
+                        for (int i = 0; i < TX; ++i)
+#pragma unroll
+                            for (int j = 0; j < TY; ++j)
+#pragma unroll
+                                for (int k = 0; k < TZ; ++k) {
+                                    const double q = a[i] + bc[j][k];
+                                    const double qi = q + l;
+                                    qtn[i][j][k] = fmin(qtn[i][j][k], q);
+                                    qtx[i][j][k] = fmax(qtx[i][j][k], q);
+                                    qin[i][j][k] = fmin(qin[i][j][k], qi);
+                                    qix[i][j][k] = fmax(qix[i][j][k], qi);
+                                }
+                    }
+                }
+            }
+
+            // exp, relaxation, trapezoid weights and the moments of this slab,
+            // reduced over the workgroup per slab (fixed order) so that no
+            // partial sums stay live across the hot loop.  The node
+            // coordinates are formed here from box values passed through an
+            // empty asm statement: otherwise the compiler hoists the
+            // slab-invariant part of this contraction out of the slab loop and
+            // keeps it live across the hot loop (register pressure).
+            double cx = lox, cy = loy, cz = loz, dx = hx, dy = hy, dz = hz;
+            asm volatile("" : "+v"(cx), "+v"(cy), "+v"(cz), "+v"(dx), "+v"(dy), "+v"(dz));
+            double ux[TX], uy[TY], uz[TZ];
+#pragma unroll
+            for (int i = 0; i < TX; ++i) ux[i] = node_pos(cx, tx + BX * i, dx);
+#pragma unroll
+            for (int j = 0; j < TY; ++j) uy[j] = node_pos(cy, ty + BY * j, dy);
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) uz[k] = node_pos(cz, z0 + tz + BZ * k, dz);
+            double part[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+#pragma unroll
+            for (int i = 0; i < TX; ++i) {
+                const int jx = tx + BX * i;
+                if (jx >= p.nx) continue;
+                const double wx = dx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const int jy = ty + BY * j;
+                    if (jy >= p.ny) continue;
+                    const double wxy = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
+#pragma unroll
+                    for (int k = 0; k < TZ; ++k) {
+                        const int jz = z0 + tz + BZ * k;
+                        if (jz >= p.nz) continue;
+                        const double M = wxy * (dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0));
+                        const double ftn = rm * exp(qtn[i][j][k]);
+                        const double ftx = rp * exp(qtx[i][j][k]);
+                        const double fin = rm * exp(qin[i][j][k]);
+                        const double fix = rp * exp(qix[i][j][k]);
+                        const double hu2 = 0.5 * ux[i] * ux[i] + 0.5 * uy[j] * uy[j] + 0.5 * uz[k] * uz[k];
+                        part[0] += M * ftn;
+                        part[1] += M * ftx;
+                        part[2] += M * (hu2 * ftn + fin);
+                        part[3] += M * (hu2 * ftx + fix);
+                        if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
+                        else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
+                        if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
+                        else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
+                        if (uz[k] < 0.0) { part[8] += M * uz[k] * ftx; part[9] += M * uz[k] * ftn; }
+                        else             { part[8] += M * uz[k] * ftn; part[9] += M * uz[k] * ftx; }
+                        // one node at a time (register pressure)
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+                }
+            }
+            block_sum<NT, 10>(part, red);
+            if (tid == 0) {
+#pragma unroll
+                for (int v = 0; v < 10; ++v) sTot[v] = (z0 == 0 ? 0.0 : sTot[v]) + part[v];
+            }
+        }
+        if (tid == 0) store_bounds<3>(p, e, sTot, flags);
+    }
+}
+
+// Tile configurations: (BX, BY, BZ, TX, TY, TZ) covers nx <= BX TX,
+// ny <= BY TY and any nz (in slabs of BZ TZ nodes).
+struct Tile3D {
+    int bx, by, bz, tx, ty, tz;
+    hipError_t (*fn)(const BoundsArgs&, hipStream_t);
+};
+
+template <int BX, int BY, int BZ, int TX, int TY, int TZ>
+hipError_t launch_3d(const BoundsArgs& a, hipStream_t stream) {
+    hipLaunchKernelGGL((bounds_fp64_3d<BX, BY, BZ, TX, TY, TZ>), dim3(bounds_grid(a)),
+                       dim3(BX * BY * BZ), 0, stream, a);
+    return hipGetLastError();
+}
+
+#define KBL_TILE3(BX, BY, BZ, TX, TY, TZ) \
+    {BX, BY, BZ, TX, TY, TZ, launch_3d<BX, BY, BZ, TX, TY, TZ>}
+constexpr Tile3D kTiles3D[] = {
+    KBL_TILE3(8, 8, 4, 2, 2, 2),     // 0: nx, ny <= 16, slabs of 8
+    KBL_TILE3(8, 8, 4, 3, 3, 1),     // 1: nx, ny <= 24, slabs of 4
+    KBL_TILE3(16, 16, 1, 2, 2, 2),   // 2: nx, ny <= 32, slabs of 2
+    KBL_TILE3(16, 16, 1, 3, 3, 1),   // 3: nx, ny <= 48, slabs of 1
+    KBL_TILE3(16, 16, 1, 4, 4, 1),   // 4: nx, ny <= 64, slabs of 1
+    KBL_TILE3(8, 8, 4, 2, 2, 4),     // 5: nx, ny <= 16, slabs of 16
+    KBL_TILE3(8, 8, 4, 3, 3, 2),     // 6: nx, ny <= 24, slabs of 8
+    KBL_TILE3(8, 8, 4, 4, 4, 1),     // 7: nx, ny <= 32, slabs of 4
+    KBL_TILE3(16, 16, 1, 3, 3, 2),   // 8: nx, ny <= 48, slabs of 2
+};
+#undef KBL_TILE3
+constexpr int kNumTiles3D = sizeof(kTiles3D) / sizeof(kTiles3D[0]);
+
+}  // namespace
+
+int bounds_tile_count_3d() { return kNumTiles3D; }
+
+bool bounds_tile_fits_3d(int tile, int nx, int ny, int nz) {
+    if (tile < 0 || tile >= kNumTiles3D || nz < 2) return false;
+    const Tile3D& t = kTiles3D[tile];
+    return nx <= t.bx * t.tx && ny <= t.by * t.ty;
+}
+
+// Defaults: the largest thread tile that still allows two waves per SIMD
+// (about nine nodes per thread); kbl_autotune_bounds may pick another.
+int bounds_default_tile_3d(int nx, int ny, int nz) {
+    (void)nz;
+    const int n = nx > ny ? nx : ny;
+    if (n <= 16) return 0;
+    if (n <= 24) return 1;
+    if (n <= 32) return 2;
+    if (n <= 48) return 3;
+    return 4;
+}
+
+hipError_t launch_bounds_fp64_3d(const BoundsArgs& a, hipStream_t stream, int tile) {
+    if (a.n_elem == 0) return hipSuccess;
+    if (tile < 0) tile = bounds_default_tile_3d(a.nx, a.ny, a.nz);
+    if (!bounds_tile_fits_3d(tile, a.nx, a.ny, a.nz)) return hipErrorInvalidValue;
+    return kTiles3D[tile].fn(a, stream);
+}
+
+}  // namespace kbl

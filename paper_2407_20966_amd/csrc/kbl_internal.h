@@ -25,8 +25,8 @@ struct BoundsArgs {
     int32_t n_s;        // nodes per source unit (1 for node-level stencils)
     int32_t grid_mode;
     int32_t energy_perstate;
-    int32_t nx, ny;
-    double lo0, lo1, hi0, hi1, k;
+    int32_t nx, ny, nz;  // velocity nodes per direction (1 past the dimension)
+    double lo0, lo1, lo2, hi0, hi1, hi2, k;
     double gm1;         // gamma - 1
     double half_delta;  // delta / 2, delta = 2/(gamma-1) - d
     double r_fac;
@@ -85,6 +85,11 @@ struct RiemannArgs {
 hipError_t launch_bounds_fp64(const BoundsArgs& a, int dim, hipStream_t stream, int tile);
 // Energy bounds from the per-state integrand (KBL_FLAG_ENERGY_PERSTATE).
 hipError_t launch_bounds_fp64_energy(const BoundsArgs& a, int dim, hipStream_t stream);
+// d = 3: FP64 bounds over a 3D velocity grid (tile < 0: default for the grid).
+hipError_t launch_bounds_fp64_3d(const BoundsArgs& a, hipStream_t stream, int tile);
+int bounds_tile_count_3d();
+bool bounds_tile_fits_3d(int tile, int nx, int ny, int nz);
+int bounds_default_tile_3d(int nx, int ny, int nz);
 int bounds_tile_count_2d();
 bool bounds_tile_fits_2d(int tile, int nx, int ny);
 int mixed_tile_count();

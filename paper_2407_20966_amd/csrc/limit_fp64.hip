@@ -45,7 +45,9 @@ __device__ __forceinline__ double grp_max(double v) {
 
 template <int D>
 __device__ __forceinline__ double pressure(double gm1, const double* w) {
-    const double mm = (D == 2) ? w[1] * w[1] + w[2] * w[2] : w[1] * w[1];
+    double mm = w[1] * w[1];
+#pragma unroll
+    for (int j = 2; j <= D; ++j) mm += w[j] * w[j];
     return gm1 * (w[D + 1] - 0.5 * mm / w[0]);
 }
 
@@ -140,10 +142,12 @@ __global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
 
 template <int D>
 __device__ __forceinline__ void pressure_grad(double gm1, const double* w, double* g) {
-    const double mm = (D == 2) ? w[1] * w[1] + w[2] * w[2] : w[1] * w[1];
+    double mm = w[1] * w[1];
+#pragma unroll
+    for (int j = 2; j <= D; ++j) mm += w[j] * w[j];
     g[0] = gm1 * 0.5 * mm / (w[0] * w[0]);
-    g[1] = -gm1 * w[1] / w[0];
-    if (D == 2) g[2] = -gm1 * w[2] / w[0];
+#pragma unroll
+    for (int j = 1; j <= D; ++j) g[j] = -gm1 * w[j] / w[0];
     g[D + 1] = gm1;
 }
 
@@ -353,6 +357,7 @@ hipError_t launch_d(const LimitArgs& a, hipStream_t stream) {
 
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream) {
     if (a.n_elem == 0) return hipSuccess;
+    if (dim == 3) return launch_d<3>(a, stream);
     return dim == 2 ? launch_d<2>(a, stream) : launch_d<1>(a, stream);
 }
 

@@ -53,7 +53,7 @@ __global__ __launch_bounds__(256) void riemann_fp64(RiemannArgs a) {
     constexpr int NV = D + 2;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < a.n_pairs;
          q += (int64_t)gridDim.x * 256) {
-        double wi[NV], wj[NV], Ui[2] = {0, 0}, Uj[2] = {0, 0}, Pi, Pj;
+        double wi[NV], wj[NV], Ui[3] = {0, 0, 0}, Uj[3] = {0, 0, 0}, Pi, Pj;
         const bool ok_i = load_state<D>(a, a.ni[q], wi, Ui, &Pi);
         const bool ok_j = load_state<D>(a, a.nj[q], wj, Uj, &Pj);
         const bool ok = ok_i && ok_j;
@@ -63,7 +63,7 @@ __global__ __launch_bounds__(256) void riemann_fp64(RiemannArgs a) {
             if (a.status) a.status[q] = KBL_RS_BAD_INPUT;
             continue;
         }
-        double n[2] = {0, 0};
+        double n[3] = {0, 0, 0};
 #pragma unroll
         for (int j = 0; j < D; ++j) n[j] = a.normals[(int64_t)j * a.n_pairs + q];
         double lam;
@@ -102,7 +102,8 @@ hipError_t launch_riemann_fp64(const RiemannArgs& a, int dim, hipStream_t stream
     if (a.n_pairs == 0) return hipSuccess;
     const int64_t blocks = (a.n_pairs + 255) / 256;
     const unsigned g = (unsigned)(blocks < 65535 * 16 ? blocks : 65535 * 16);
-    if (dim == 2) hipLaunchKernelGGL(riemann_fp64<2>, dim3(g), dim3(256), 0, stream, a);
+    if (dim == 3) hipLaunchKernelGGL(riemann_fp64<3>, dim3(g), dim3(256), 0, stream, a);
+    else if (dim == 2) hipLaunchKernelGGL(riemann_fp64<2>, dim3(g), dim3(256), 0, stream, a);
     else hipLaunchKernelGGL(riemann_fp64<1>, dim3(g), dim3(256), 0, stream, a);
     return hipGetLastError();
 }

@@ -31,14 +31,16 @@ def make_params(gamma: float, r_fac: float = 1e-3, rho_floor: float = 1e-12,
     return p
 
 
-def make_vgrid(mode: int, n: Sequence[int], lo: Sequence[float] = (0.0, 0.0),
-               hi: Sequence[float] = (0.0, 0.0), k: float = 4.0) -> L.VGrid:
+def make_vgrid(mode: int, n: Sequence[int], lo: Sequence[float] = (0.0, 0.0, 0.0),
+               hi: Sequence[float] = (0.0, 0.0, 0.0), k: float = 4.0) -> L.VGrid:
+    """Velocity grid (Sec. 3.7): nodes per direction `n` (one entry per
+    dimension), the GLOBAL box [lo, hi], or the STENCIL extent `k`."""
     g = L.VGrid()
     g.mode = int(mode)
-    nn = list(n) + [2] * (2 - len(n))
-    lo = list(lo) + [0.0] * (2 - len(lo))
-    hi = list(hi) + [0.0] * (2 - len(hi))
-    for j in range(2):
+    nn = list(n) + [2] * (3 - len(n))
+    lo = list(lo) + [0.0] * (3 - len(lo))
+    hi = list(hi) + [0.0] * (3 - len(hi))
+    for j in range(3):
         g.n[j] = int(nn[j])
         g.lo[j] = float(lo[j])
         g.hi[j] = float(hi[j])

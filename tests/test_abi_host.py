@@ -93,7 +93,7 @@ def _bounds(lib, p, g, dim=2, n_elem=4, n_s=16, nnz=20, ptrs=True):
 
 
 @pytest.mark.parametrize("case,expect", [
-    (dict(dim=3), L.KBL_ERR_ARG),
+    (dict(dim=4), L.KBL_ERR_ARG),
     (dict(dim=0), L.KBL_ERR_ARG),
     (dict(n_elem=-1), L.KBL_ERR_ARG),
     (dict(n_s=0), L.KBL_ERR_ARG),
@@ -252,10 +252,55 @@ def _riemann(lib, p, dim=2, n_pairs=4, n_nodes=8, bounds=None, elem=None, n_elem
 
 def test_riemann_rejects_bad_arguments(lib):
     p = _params(lib)
-    assert _riemann(lib, p, dim=3) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, dim=4) == L.KBL_ERR_ARG
     assert _riemann(lib, p, n_pairs=-1) == L.KBL_ERR_ARG
     assert _riemann(lib, p, ptrs=False) == L.KBL_ERR_ARG
     assert _riemann(lib, p, bounds=FAKE, elem=None, n_elem=4) == L.KBL_ERR_ARG
     assert _riemann(lib, p, bounds=FAKE, elem=FAKE, n_elem=0) == L.KBL_ERR_ARG
     assert _riemann(lib, _params(lib, 1.0)) == L.KBL_ERR_GAMMA
     assert _riemann(lib, p, n_pairs=0, ptrs=False) == L.KBL_OK      # nothing to do, no launch
+
+
+def _grid3(mode=L.GRID_STENCIL, n=(24, 24, 24), k=4.0):
+    g = L.VGrid()
+    g.mode = mode
+    for j in range(3):
+        g.n[j] = n[j]
+        g.lo[j], g.hi[j] = -1.0, 1.0
+    g.k = k
+    return g
+
+
+def test_three_dimensional_rejections(lib):
+    # every case returns before any launch (the pointers are fake)
+    p = _params(lib)
+    assert _bounds(lib, p, _grid3(n=(24, 24, 1)), dim=3, n_s=27) == L.KBL_ERR_GRID
+    assert _bounds(lib, p, _grid3(n=(24, 65, 24)), dim=3, n_s=27) == L.KBL_ERR_GRID
+    assert _bounds(lib, p, _grid3(n=(24, 24, 65)), dim=3, n_s=27) == L.KBL_ERR_GRID
+    # delta = 2/(gamma-1) - 3 < 0 for gamma > 5/3
+    assert _bounds(lib, _params(lib, 1.7), _grid3(), dim=3, n_s=27) == L.KBL_ERR_GAMMA
+    for prec in (L.PREC_MIXED_BF16, L.PREC_MIXED_FP16, L.PREC_MIXED_FP32):
+        assert _bounds(lib, _params(lib, precision=prec), _grid3(), dim=3, n_s=27) == L.KBL_ERR_UNSUPPORTED
+        assert _autotune(lib, _params(lib, precision=prec), _grid3(), dim=3, n_s=27) == -1
+    pe = _params(lib, flags=L.FLAG_ENERGY_PERSTATE)
+    assert _bounds(lib, pe, _grid3(), dim=3, n_s=27) == L.KBL_ERR_UNSUPPORTED
+    assert _autotune(lib, pe, _grid3(), dim=3, n_s=27) == -1
+    assert _backward(lib, p, _grid3(), dim=3, n_s=27) == L.KBL_ERR_UNSUPPORTED
+    assert lib.kbl_backward_workspace_bytes(3, 10, 27, 10) == 0
+    assert _bounds(lib, p, _grid3(), dim=3, n_s=27, ptrs=False) == L.KBL_ERR_ARG
+    assert _riemann(lib, p, dim=3, ptrs=False) == L.KBL_ERR_ARG
+    assert _limit(lib, p, [1.0] * 27, dim=3, n_elem=-1) == L.KBL_ERR_ARG
+
+
+def _tile_table(src, macro):
+    import re
+    text = open(os.path.join(ROOT, "paper_2407_20966_amd", "csrc", src)).read()
+    rows = re.findall(rf"^\s*{macro}\(([^)]*)\),", text, flags=re.M)
+    return {i: tuple(int(x) for x in r.split(",")) for i, r in enumerate(rows)}
+
+
+def test_python_tile_tables_match_the_kernels():
+    # the tile indices accepted by KBL_BOUNDS_TILE / KBL_MIXED_TILE and
+    # returned by kbl_autotune_bounds are positions in these tables
+    assert _tile_table("bounds_fp64.hip", "KBL_TILE") == L.FP64_TILES
+    assert _tile_table("bounds_fp64_3d.hip", "KBL_TILE3") == L.FP64_TILES_3D

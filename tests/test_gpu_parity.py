@@ -162,11 +162,16 @@ def test_inadmissible_and_bad_rows(kbl):
     wl.states[1, 20 * 16 + 2] = np.nan
     wl.cols = wl.cols.copy()
     wl.cols[5 * 7 + 2] = wl.n_elem + 3          # out-of-range element id in row 7
+    # a bad row that also lists the inadmissible element 10: reported as a bad row alone
+    r = next(e for e in range(wl.n_elem) if e != 10 and 10 in wl.cols[5 * e:5 * e + 5])
+    j = next(j for j in range(5) if wl.cols[5 * r + j] != 10)
+    wl.cols[5 * r + j] = -1
     wl.rowptr = wl.rowptr.copy()
     b, s, lim, al, ls = run_gpu(kbl, wl)
     rb, rs = oracle.workload_bounds(wl)
     assert np.array_equal(s, rs)
     assert s[7] & kbl.ST_BAD_STENCIL
+    assert s[r] == kbl.ST_BAD_STENCIL
     assert (s[10] & kbl.ST_INADMISSIBLE) and (s[20] & kbl.ST_INADMISSIBLE)
     assert np.array_equal(np.isnan(b), np.isnan(rb))
     good = ~np.isnan(rb).any(0)
