@@ -47,34 +47,42 @@ WORKLOAD_TEXT = {
                 "per-stencil velocity grid (k=4), 4-quadrant Riemann field"),
     "line64": ("1D Euler gamma=1.4, 64 elements, p=3, 12-state stencils, 64-node global velocity "
                "grid on [-12,12] sqrt(theta_max), sine + Sod jump"),
+    "hex32": ("3D Euler gamma=1.4, 32^3 periodic hexahedra, p=2 (3x3x3 Gauss-Legendre nodes), "
+              "7-element face stencils (189 states), 24^3 per-stencil velocity grid (k=4), "
+              "r_fac=1e-3, 8-octant Riemann field rho in [0.1,10], p in [0.1,100], |U|<=3 "
+              "+1% smooth perturbation"),
 }
 
 
-KERNEL_SOURCES = ("paper_2407_20966_amd/csrc/bounds_fp64.hip",
-                  "paper_2407_20966_amd/csrc/bounds_common.h",
-                  "paper_2407_20966_amd/csrc/kbl_internal.h")
-TRAFFIC_FILE = "profiles/bounds_fp64_2d_traffic.txt"
+# sources of the FP64 bounds kernels, per velocity dimension
+KERNEL_SOURCES = {
+    2: ("paper_2407_20966_amd/csrc/bounds_fp64.hip", "paper_2407_20966_amd/csrc/bounds_common.h",
+        "paper_2407_20966_amd/csrc/kbl_internal.h"),
+    3: ("paper_2407_20966_amd/csrc/bounds_fp64_3d.hip",
+        "paper_2407_20966_amd/csrc/bounds_common.h", "paper_2407_20966_amd/csrc/kbl_internal.h"),
+}
+TRAFFIC_FILE = "profiles/bounds_fp64_traffic.txt"
 
 
-def kernel_sources_sha() -> str:
+def kernel_sources_sha(dim: int) -> str:
     """sha256 of the FP64 bounds kernel's sources (identifies what was profiled)."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[dim]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
 
-def profiled_traffic(kernel: str, grid_threads: int, workload: str):
+def profiled_traffic(kernel: str, grid_threads: int, workload: str, dim: int):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is
     no entry for this kernel, launch shape and workload, or the kernel's
-    sources changed since the counters were taken."""
+    sources changed since the counters were taken (per-entry sha256)."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
-    if not os.path.exists(path):
+    if not os.path.exists(path) or dim not in KERNEL_SOURCES:
         return None
-    head, entries, cur = {}, [], None
+    entries, cur = [], None
     for line in open(path):
         line = line.strip()
         if not line or line.startswith("#"):
@@ -83,15 +91,14 @@ def profiled_traffic(kernel: str, grid_threads: int, workload: str):
             cur = {}
             entries.append(cur)
             continue
-        if "=" in line:
+        if "=" in line and cur is not None:
             k, v = line.split("=", 1)
-            (head if cur is None else cur)[k.strip()] = v.strip()
-    if head.get("source_sha256") != kernel_sources_sha():
-        return None
+            cur[k.strip()] = v.strip()
+    sha = kernel_sources_sha(dim)
     for e in entries:
         try:
             if (e["kernel"] == kernel and int(e["grid_threads"]) == grid_threads
-                    and e["workload"] == workload):
+                    and e["workload"] == workload and e["source_sha256"] == sha):
                 return float(e["bytes_per_launch"])
         except (KeyError, ValueError):
             continue
@@ -102,10 +109,25 @@ def pair_ops(dim: int) -> int:
     """Algorithmic VALU lane-ops per (stencil state, velocity node) pair.
 
     2D: the log-Maxwellian is separable, q = A[jx] + B[jy]: two adds (q and
-    q + ln(theta delta/2)) and four running min/max.  1D: sub, mul, fma, fma,
-    then four min/max.
+    q + ln(theta delta/2)) and four running min/max.  3D: the same with
+    q = A[jx] + (B[jy] + C[jz]), the bracket shared by all x nodes (its add
+    is not counted).  1D: sub, mul, fma, fma, then four min/max.
     """
-    return 6 if dim == 2 else 8
+    return 8 if dim == 1 else 6
+
+
+def kernel_shape(kbl, dim, tuned, n_elem, n_cu):
+    """Kernel name and grid threads of the FP64 bounds launch for an
+    autotuned choice (None, None without one)."""
+    if dim == 1 or not tuned:
+        return ("bounds_fp64_1d" if dim == 1 else f"bounds_fp64_{dim}d"), None
+    wpc = tuned["workgroups_per_cu"]
+    blocks = n_elem if wpc == 0 else min(n_elem, wpc * n_cu)
+    if dim == 2:
+        bx, by, tx, ty, md = kbl._lib.FP64_TILES[tuned["tile"]]
+        return f"bounds_fp64_2d<{bx}, {by}, {tx}, {ty}, {md}>", blocks * bx * by
+    bx, by, bz, tx, ty, tz = kbl._lib.FP64_TILES_3D[tuned["tile"]]
+    return f"bounds_fp64_3d<{bx}, {by}, {bz}, {tx}, {ty}, {tz}>", blocks * bx * by * bz
 
 
 def cpu_baseline(wl, target_s: float = 12.0):
@@ -259,6 +281,66 @@ def time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream, ms_st
     return out
 
 
+def time_3d(args, kbl, torch, synth, stream):
+    """The same step on a 3D velocity grid (hex32): the d = 3 kernel whose cost
+    the paper's conclusion flags."""
+    dev = torch.device("cuda:0")
+    print("[bench] generating hex32", file=sys.stderr, flush=True)
+    wl = synth.make_workload("hex32")
+    g = wl.grid
+    st = torch.from_numpy(wl.states).to(dev)
+    rp = torch.from_numpy(wl.rowptr).to(dev)
+    cl = torch.from_numpy(wl.cols).to(dev)
+    tg = torch.from_numpy(wl.target).to(dev)
+    vg = kbl.make_vgrid(g.mode, g.n[:3], g.lo, g.hi, g.k)
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    bnd = torch.empty((10, wl.n_elem), dtype=torch.float64, device=dev)
+    bst = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+    lim = torch.empty_like(tg)
+    tuned = None
+    if not args.no_autotune:
+        c = kbl.autotune_bounds(st, rp, cl, wl.n_s, vg, prm, sample_elems=8192, stream=stream)
+        tuned = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
+        print(f"[bench] autotuned hex32: {tuned}", file=sys.stderr, flush=True)
+    steps = max(2, args.steps // 2)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+
+    def step(e=None):
+        if e is not None:
+            e[0].record(stream)
+        kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm, out=bnd, status=bst, stream=stream)
+        if e is not None:
+            e[1].record(stream)
+        kbl.limit(tg, bnd, wl.node_weights, wl.n_s, prm, out=lim, stream=stream)
+        if e is not None:
+            e[2].record(stream)
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(ev[i])
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / steps
+    b_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    l_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    kname, gthreads = kernel_shape(kbl, 3, tuned, wl.n_elem, n_cu)
+    ops = wl.pairs() * pair_ops(3)
+    print(f"[bench] hex32: {ms:.3f} ms/step (bounds {b_ms:.3f} ms, limit {l_ms:.3f} ms)",
+          file=sys.stderr, flush=True)
+    traffic = profiled_traffic(kname, gthreads, "hex32", 3) if gthreads else None
+    out = {"workload": f"hex32: {WORKLOAD_TEXT['hex32']}", "n_elem": wl.n_elem,
+           "value": wl.n_elem / (ms * 1e-3), "unit": "elements/s", "ms_per_step": ms,
+           "bounds_ms": b_ms, "limit_ms": l_ms, "kernel": kname, "grid_threads": gthreads,
+           "pairs_per_launch": wl.pairs(), "ops_per_pair": pair_ops(3),
+           "frac": ops / (b_ms * 1e-3) / VALU_PEAK_OPS, "traffic": traffic,
+           "traffic_unit": "bytes per launch", "launch": tuned, "parity_tol": 1e-12}
+    del st, tg, lim
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -269,6 +351,7 @@ def main(argv=None):
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
     ap.add_argument("--no-fr", action="store_true", help="skip the node-level stencil timing")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D velocity-grid timing")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variant timings (energy reading, r = 0, independent "
                          "limiting, node-level stencils)")
@@ -355,15 +438,10 @@ def main(argv=None):
     pairs = wl.pairs()
     ops = pairs * pair_ops(wl.dim)
     achieved = ops / (b_ms * 1e-3)
-    kname, grid_threads = "bounds_fp64_2d" if wl.dim == 2 else "bounds_fp64_1d", None
-    if wl.dim == 2 and "fp64" in tuned:
-        bx, by, tx, ty, md = kbl._lib.FP64_TILES[tuned["fp64"]["tile"]]
-        kname = f"bounds_fp64_2d<{bx}, {by}, {tx}, {ty}, {md}>"
-        wpc = tuned["fp64"]["workgroups_per_cu"]
-        blocks = wl.n_elem if wpc == 0 else min(wl.n_elem, wpc * torch.cuda.get_device_properties(
-            dev).multi_processor_count)
-        grid_threads = blocks * bx * by
-    traffic = profiled_traffic(kname, grid_threads, args.workload) if grid_threads else None
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
+    kname, grid_threads = kernel_shape(kbl, wl.dim, tuned.get("fp64"), wl.n_elem, n_cu)
+    traffic = (profiled_traffic(kname, grid_threads, args.workload, wl.dim)
+               if grid_threads else None)
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
             "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_FILE,
@@ -424,7 +502,7 @@ def main(argv=None):
                                    "note": "workgroups_per_cu 0 = one workgroup per element"}
     # the hand-written backward of bounds + limiter, J = sum w rho_limited; the
     # forward's bounds and status are handed over (as the autograd Function does)
-    if not args.no_backward:
+    if not args.no_backward and wl.dim <= 2:
         G = torch.zeros_like(tg)
         G[0] = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n_nodes)).to(dev)
 
@@ -475,6 +553,8 @@ def main(argv=None):
     if not args.no_variants and wl.dim == 2:
         out["variants"] = time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream,
                                         ms_step, b_ms)
+    if not args.no_3d and wl.dim == 2:
+        out["three_d"] = time_3d(args, kbl, torch, synth, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
