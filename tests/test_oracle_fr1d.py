@@ -1,0 +1,255 @@
+"""Pins of the 1D flux reconstruction reference solver (oracle/fr1d.py) and the
+exact Riemann solver (oracle/exact_riemann.py), against what the mathematics
+fixes: polynomial exactness, the Radau (DG) property of the correction
+functions, equality with an independently written nodal DG weak form, HLLC
+consistency and contact resolution, free-stream preservation, conservation,
+the design order on a smooth problem, the limiter's bounds and mean
+preservation inside SSP-RK3 (Sec. 5), and the Rankine-Hugoniot / isentropic
+relations of the exact solution."""
+
+import numpy as np
+import pytest
+
+from oracle import exact_riemann as ER
+from oracle import fr1d
+
+GAMMA = 1.4
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_lagrange_operators_exact_on_polynomials(p):
+    xi, _ = fr1d.gl_nodes(p)
+    at_m1, at_p1, D = fr1d.lagrange_operators(xi)
+    rng = np.random.default_rng(p)
+    c = rng.standard_normal(p + 1)
+    f = np.polynomial.polynomial.polyval(xi, c)
+    df = np.polynomial.polynomial.polyval(xi, np.polynomial.polynomial.polyder(c))
+    np.testing.assert_allclose(D @ f, df, atol=1e-12 * np.abs(c).sum() * (p + 1) ** 2)
+    np.testing.assert_allclose(at_m1 @ f, np.polynomial.polynomial.polyval(-1.0, c), atol=1e-12)
+    np.testing.assert_allclose(at_p1 @ f, np.polynomial.polynomial.polyval(1.0, c), atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 4, 5])
+def test_dg_correction_functions(p):
+    L = np.polynomial.legendre
+    gL, gR = fr1d.correction_functions(p)
+    assert abs(L.legval(-1.0, gL) - 1.0) < 1e-14 and abs(L.legval(1.0, gL)) < 1e-14
+    assert abs(L.legval(1.0, gR) - 1.0) < 1e-14 and abs(L.legval(-1.0, gR)) < 1e-14
+    # Radau property: orthogonal to every polynomial of degree p - 1
+    x, w = L.leggauss(p + 3)
+    for q in range(p):
+        Pq = L.legval(x, np.eye(q + 1)[q])
+        assert abs(np.sum(w * L.legval(x, gL) * Pq)) < 1e-13
+        assert abs(np.sum(w * L.legval(x, gR) * Pq)) < 1e-13
+
+
+def random_states(rng, shape, gamma=GAMMA, spread=1.0):
+    rho = np.exp(rng.uniform(-spread, spread, shape))
+    u = rng.uniform(-spread, spread, shape)
+    P = np.exp(rng.uniform(-spread, spread, shape))
+    return fr1d.conserved(rho, u, P, gamma)
+
+
+def smooth_states(rng, n, p, gamma=GAMMA):
+    """Nodal states with a moderate spread, so that the end values of every
+    element polynomial stay admissible."""
+    rho = np.exp(rng.uniform(-1, 1, (n, 1))) * (1 + 0.05 * rng.uniform(-1, 1, (n, p + 1)))
+    u = rng.uniform(-1, 1, (n, 1)) + 0.05 * rng.uniform(-1, 1, (n, p + 1))
+    P = np.exp(rng.uniform(-1, 1, (n, 1))) * (1 + 0.05 * rng.uniform(-1, 1, (n, p + 1)))
+    return fr1d.conserved(rho, u, P, gamma)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5])
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_fr_equals_nodal_dg_weak_form(p, bc):
+    # FR with the DG correction functions is the nodal DG method with
+    # Gauss-Legendre quadrature at the solution points:
+    #   w_j h/2 du_j/dt = sum_k w_k l_j'(x_k) F_k - (F*_R l_j(1) - F*_L l_j(-1))
+    rng = np.random.default_rng(10 + p)
+    n = 7
+    s = fr1d.FR1D(p, n, 0.0, 2.0, GAMMA, bc=bc, left=random_states(rng, ()),
+                  right=random_states(rng, ()))
+    U = smooth_states(rng, n, p)
+    R = s.rhs(U)
+    assert np.isfinite(R).all()
+    F = fr1d.euler_flux(U, GAMMA)
+    uL, uR = s.faces(U)
+    nxt = np.roll(uL, -1, axis=1)
+    prv = np.roll(uR, 1, axis=1)
+    if bc == "dirichlet":
+        nxt[:, -1] = s.right
+        prv[:, 0] = s.left
+    FsR = fr1d.hllc_flux(uR, nxt, GAMMA)
+    FsL = fr1d.hllc_flux(prv, uL, GAMMA)
+    xi, w = s.xi, s.w
+    # l_j'(x_k) = D[k, j]
+    vol = np.einsum("k,kj,vek->vej", w, s.D, F)
+    surf = FsR[:, :, None] * s.at_p1[None, None, :] - FsL[:, :, None] * s.at_m1[None, None, :]
+    Rdg = (vol - surf) / (w[None, None, :] * 0.5 * s.h)
+    np.testing.assert_allclose(R, Rdg, rtol=1e-11, atol=1e-11 * np.abs(Rdg).max())
+
+
+def test_hllc_consistency_symmetry_and_contact():
+    rng = np.random.default_rng(3)
+    U = random_states(rng, (50,))
+    np.testing.assert_allclose(fr1d.hllc_flux(U, U, GAMMA), fr1d.euler_flux(U, GAMMA),
+                               rtol=1e-13, atol=1e-13)
+    UL, UR = random_states(rng, (50,)), random_states(rng, (50,))
+    F = fr1d.hllc_flux(UL, UR, GAMMA)
+    mirror = np.array([1.0, -1.0, 1.0])[:, None]
+    Fm = fr1d.hllc_flux(UR * mirror, UL * mirror, GAMMA)
+    # reflection x -> -x: mass and energy fluxes change sign, momentum flux does not
+    np.testing.assert_allclose(Fm, -F * mirror, rtol=1e-12, atol=1e-12)
+    # an isolated stationary contact is resolved exactly: flux (0, p, 0)
+    cL = fr1d.conserved(np.array([1.0]), 0.0, 0.7, GAMMA)
+    cR = fr1d.conserved(np.array([0.1]), 0.0, 0.7, GAMMA)
+    np.testing.assert_allclose(fr1d.hllc_flux(cL, cR, GAMMA)[:, 0], [0.0, 0.7, 0.0], atol=1e-15)
+    # supersonic flow to the right takes the left flux
+    sL = fr1d.conserved(np.array([1.0]), 5.0, 1.0, GAMMA)
+    sR = fr1d.conserved(np.array([0.5]), 4.0, 0.5, GAMMA)
+    np.testing.assert_allclose(fr1d.hllc_flux(sL, sR, GAMMA), fr1d.euler_flux(sL, GAMMA))
+
+
+@pytest.mark.parametrize("p", [2, 4])
+def test_free_stream_and_conservation(p):
+    s = fr1d.FR1D(p, 9, -0.5, 0.5, GAMMA)
+    U = np.broadcast_to(fr1d.conserved(np.array(0.8), 0.3, 1.3, GAMMA)[:, None, None],
+                        (3, 9, p + 1)).copy()
+    assert np.abs(s.rhs(U)).max() < 1e-12
+    rng = np.random.default_rng(p)
+    U = smooth_states(rng, 9, p)
+    assert np.isfinite(s.rhs(U)).all()
+    total = np.einsum("vej,j->v", s.rhs(U), s.w) * 0.5 * s.h
+    assert np.abs(total).max() < 1e-11 * np.abs(s.rhs(U)).max()
+
+
+def pulse(s, t=0.0, sigma=100.0):
+    x = s.node_x()
+    xs = (x - t + 0.5) % 1.0 - 0.5
+    return fr1d.conserved(1.0 + np.exp(-sigma * xs ** 2), 1.0, 1.0, GAMMA)
+
+
+def run(s, U, t_end, cfl, limiter, **kw):
+    t = 0.0
+    while t < t_end - 1e-14:
+        dt = min(cfl * s.h / ((2 * s.p + 1) * s.max_speed(U)), t_end - t)
+        U = s.step(U, dt, limiter=limiter, **kw)
+        t += dt
+    return U
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_design_order_on_a_smooth_pulse(p):
+    # unlimited FR on the convecting pulse: L_inf error falls at about p + 1
+    errs = []
+    for n in (8, 16):
+        s = fr1d.FR1D(p, n, -0.5, 0.5, GAMMA)
+        U = run(s, pulse(s), 0.25, 0.3, False)
+        errs.append(np.abs(U[0] - pulse(s, 0.25)[0]).max())
+    rate = np.log2(errs[0] / errs[1])
+    assert rate > p + 0.5, (errs, rate)
+
+
+def test_limited_step_keeps_means_and_bounds():
+    # Sod-type data, periodic: the updated state of a stage is limited into
+    # the kinetic bounds of the input state's node stencils (Sec. 3.9); the
+    # limiter keeps element means, so the total of each conserved variable is
+    # that of the unlimited update
+    p, n = 3, 12
+    s = fr1d.FR1D(p, n, 0.0, 1.0, GAMMA)
+    x = s.node_x()
+    U = fr1d.conserved(np.where(np.abs(x - 0.5) < 0.25, 1.0, 0.125), 0.0,
+                       np.where(np.abs(x - 0.5) < 0.25, 1.0, 0.1), GAMMA)
+    dt = 0.2 * s.h / ((2 * p + 1) * s.max_speed(U))
+    b, st = s.bounds(U, n_u=256)
+    assert not (st & 0x101).any()
+    U1u = U + dt * s.rhs(U)
+    U1, alpha, lst = s.limit_into(U1u, b, return_info=True)
+    np.testing.assert_allclose(s.mean(U1), s.mean(U1u), rtol=1e-13, atol=1e-14)
+    assert (alpha[0] < 1).any()
+    V = s.v_states(U1).reshape(3, n, p + 3)
+    tol = 1e-12 * np.abs(b).max(0)
+    # every mean inside its bounds (the CFL condition); constant elements take
+    # the epsilon rule (alpha = 0), which leaves them at their mean
+    assert not (lst[:n] & 0x40).any()
+    assert np.all(V.min(2) >= b[:3, :n] - tol[:n])
+    assert np.all(V.max(2) <= b[3:, :n] + tol[:n])
+    U2 = s.step(U, dt, n_u=256)
+    assert np.all(U2[0] > 0) and np.all(fr1d.pressure(U2, GAMMA) > 0)
+    np.testing.assert_allclose(s.mean(U2).sum(1), s.mean(U).sum(1), rtol=1e-12, atol=1e-13)
+
+
+def test_initial_limiting_makes_end_values_admissible():
+    # a jump at an element centre: the end values of the nodal interpolant
+    # overshoot to negative density and pressure; limiting into the bounds of
+    # the neighbouring solution points brings every node of V into G
+    p, n = 2, 21
+    s = fr1d.FR1D(p, n, 0.0, 1.0, GAMMA, bc="dirichlet", left=fr1d.conserved(np.array(1.0), 0, 1, GAMMA),
+                  right=fr1d.conserved(np.array(0.125), 0, 0.1, GAMMA))
+    x = s.node_x()
+    U = fr1d.conserved(np.where(x <= 0.5, 1.0, 0.125), 0.0, np.where(x <= 0.5, 1.0, 0.1), GAMMA)
+    V = s.v_states(U).reshape(3, -1, p + 3)
+    assert (V[0] < 0).any()
+    Ul = s.limit_initial(U, n_u=256)
+    V = s.v_states(Ul).reshape(3, -1, p + 3)
+    assert (V[0] > 0).all() and (fr1d.pressure(V, GAMMA) > 0).all()
+    np.testing.assert_allclose(s.mean(Ul), s.mean(U), rtol=1e-13, atol=1e-15)
+
+
+def test_dirichlet_ghosts_in_the_stencil():
+    s = fr1d.FR1D(2, 4, 0.0, 1.0, GAMMA, bc="dirichlet", left=[1.0, 0.0, 2.5],
+                  right=[0.125, 0.0, 0.25])
+    n_v, n_tot, rowptr, cols = s.stencil_layout()
+    assert n_tot == 6 and n_v == 5
+    _, _, rp0, cl0 = s.stencil_layout(initial=True)
+    assert list(cl0[rp0[0]:rp0[1]]) == [0, 1, 2, 20, 21, 22, 5, 6, 7]
+    assert list(cols[rowptr[0]:rowptr[1]][-2:]) == [4 * 5 + 4, 1 * 5 + 3]
+    assert list(cols[rowptr[3]:rowptr[4]][-2:]) == [2 * 5 + 4, 5 * 5 + 3]
+    assert list(cols[rowptr[4]:rowptr[5]]) == list(range(20, 25))
+
+
+# ---------------------------------------------------------------- exact Riemann
+
+SOD = ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1))
+
+
+def test_exact_riemann_wave_relations():
+    WL, WR = SOD
+    g = GAMMA
+    ps, us = ER.star_state(WL, WR, g)
+    # sample finely; left rarefaction, contact, right shock
+    s = np.linspace(-2.0, 2.0, 40001)
+    rho, u, p = ER.sample(WL, WR, g, s)
+    # contact: pressure and velocity continuous, density jumps
+    i = np.searchsorted(s, us)
+    assert abs(p[i - 2] - p[i + 2]) < 1e-12 and abs(u[i - 2] - u[i + 2]) < 1e-12
+    assert rho[i - 2] > rho[i + 2]
+    # right shock: Rankine-Hugoniot with the shock speed from the jump
+    j = np.nonzero(np.abs(np.diff(rho)) > 1e-3)[0][-1]
+    a, b = (rho[j], u[j], p[j]), (rho[j + 1], u[j + 1], p[j + 1])
+    S = (a[0] * a[1] - b[0] * b[1]) / (a[0] - b[0])
+    def flux(W):
+        r, v, P = W
+        E = P / (g - 1) + 0.5 * r * v * v
+        return np.array([r * v, r * v * v + P, (E + P) * v]), np.array([r, r * v, E])
+    Fa, Ua = flux(a)
+    Fb, Ub = flux(b)
+    np.testing.assert_allclose(Fa - Fb, S * (Ua - Ub), rtol=1e-10, atol=1e-12)
+    # left rarefaction: u + 2c/(g-1) and p / rho^g constant through the fan
+    fan = (s > -1.2) & (s < us - 0.1)
+    c = np.sqrt(g * p[fan] / rho[fan])
+    J = u[fan] + 2 * c / (g - 1)
+    np.testing.assert_allclose(J, J[0], rtol=1e-12)
+    np.testing.assert_allclose(p[fan] / rho[fan] ** g, WL[2] / WL[0] ** g, rtol=1e-12)
+
+
+def test_exact_riemann_mirror_and_trivial():
+    WL, WR = (0.5, 0.2, 0.4), (1.2, -0.3, 2.0)
+    s = np.linspace(-3, 3, 601)
+    r1, u1, p1 = ER.sample(WL, WR, GAMMA, s)
+    r2, u2, p2 = ER.sample((WR[0], -WR[1], WR[2]), (WL[0], -WL[1], WL[2]), GAMMA, -s)
+    np.testing.assert_allclose(r1, r2, rtol=1e-12)
+    np.testing.assert_allclose(u1, -u2, rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(p1, p2, rtol=1e-12)
+    r, u, p = ER.sample((0.7, 0.1, 0.9), (0.7, 0.1, 0.9), GAMMA, s)
+    assert np.allclose(r, 0.7) and np.allclose(u, 0.1) and np.allclose(p, 0.9)
