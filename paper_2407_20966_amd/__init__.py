@@ -12,10 +12,11 @@ from ._lib import (  # noqa: F401
     ST_MEAN_OUTSIDE, ST_BAD_BOUNDS, ST_BAD_STENCIL, ST_TOO_LARGE, ST_ASYMMETRIC, KblError,
     LIB_PATH,
 )
+from .fr1d import FR1D  # noqa: F401
 from .ops import (  # noqa: F401
     KineticBoundsLimit, autotune_bounds, bounds_and_limit, bounds_limit_backward,
     compute_bounds, compute_bounds_nodes, limit, make_params, make_vgrid, riemann_states,
 )
 
 __all__ = ["compute_bounds", "compute_bounds_nodes", "limit", "riemann_states", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
-           "KineticBoundsLimit", "make_params", "make_vgrid", "KblError"]
+           "KineticBoundsLimit", "make_params", "make_vgrid", "KblError", "FR1D"]

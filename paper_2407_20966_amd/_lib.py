@@ -9,6 +9,7 @@ import re
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkbl.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "kbl.h")
+HEADERS = (HEADER, os.path.join(os.path.dirname(HERE), "include", "kbl_fr1d.h"))
 
 KBL_OK = 0
 KBL_ERR_ARG = 1
@@ -67,6 +68,17 @@ class Params(C.Structure):
                 ("flags", C.c_int32)]
 
 
+FR_PERIODIC = 0
+FR_DIRICHLET = 1
+FR_MAX_DEGREE = 7
+
+
+class Fr1dCfg(C.Structure):
+    _fields_ = [("p", C.c_int32), ("bc", C.c_int32), ("n_elem", C.c_int64), ("x0", C.c_double),
+                ("x1", C.c_double), ("left", C.c_double * 3), ("right", C.c_double * 3),
+                ("limit", C.c_int32), ("reserved", C.c_int32)]
+
+
 class KblError(RuntimeError):
     def __init__(self, code: int, where: str):
         self.code = code
@@ -78,8 +90,8 @@ _lib = None
 
 
 def header_symbols():
-    """Entry points declared in include/kbl.h."""
-    txt = open(HEADER).read()
+    """Entry points declared in include/kbl.h and include/kbl_fr1d.h."""
+    txt = "".join(open(h).read() for h in HEADERS)
     return sorted(set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(kbl_\w+)\s*\(", txt, flags=re.M)))
 
 
@@ -123,6 +135,21 @@ def _load():
                                                   C.POINTER(VGrid), P, P, P, P, P, P, P, P,
                                                   P, P, C.c_size_t, P]
         lib.kbl_bounds_limit_backward.restype = C.c_int
+        F = C.POINTER(Fr1dCfg)
+        lib.kbl_fr1d_columns.argtypes = [F]
+        lib.kbl_fr1d_columns.restype = C.c_int64
+        lib.kbl_fr1d_workspace_bytes.argtypes = [F]
+        lib.kbl_fr1d_workspace_bytes.restype = C.c_size_t
+        lib.kbl_fr1d_rhs.argtypes = [F, C.c_double, P, P, P]
+        lib.kbl_fr1d_rhs.restype = C.c_int
+        lib.kbl_fr1d_limit.argtypes = [F, C.POINTER(Params), C.POINTER(VGrid), P, P, C.c_size_t,
+                                       P, P]
+        lib.kbl_fr1d_limit.restype = C.c_int
+        lib.kbl_fr1d_step.argtypes = [F, C.POINTER(Params), C.POINTER(VGrid), C.c_double, P, P,
+                                      C.c_size_t, P, P]
+        lib.kbl_fr1d_step.restype = C.c_int
+        lib.kbl_fr1d_max_speed.argtypes = [F, C.c_double, P, P, P]
+        lib.kbl_fr1d_max_speed.restype = C.c_int
         _lib = lib
     return _lib
 

@@ -304,3 +304,81 @@ def test_python_tile_tables_match_the_kernels():
     # returned by kbl_autotune_bounds are positions in these tables
     assert _tile_table("bounds_fp64.hip", "KBL_TILE") == L.FP64_TILES
     assert _tile_table("bounds_fp64_3d.hip", "KBL_TILE3") == L.FP64_TILES_3D
+
+
+# ---------------------------------------------------------------- 1D FR solver
+
+def _fr_cfg(**kw):
+    c = L.Fr1dCfg()
+    c.p, c.bc, c.n_elem, c.x0, c.x1, c.limit, c.reserved = 3, L.FR_PERIODIC, 16, 0.0, 1.0, 1, 0
+    for k, v in kw.items():
+        if k in ("left", "right"):
+            for i in range(3):
+                getattr(c, k)[i] = v[i]
+        else:
+            setattr(c, k, v)
+    return c
+
+
+def test_fr1d_struct_layout_matches_c(tmp_path):
+    src = tmp_path / "fr.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "kbl_fr1d.h"\n'
+        "int main(void){\n"
+        ' printf("%zu %zu %zu %zu %zu\\n", sizeof(kbl_fr1d), offsetof(kbl_fr1d, n_elem),'
+        " offsetof(kbl_fr1d, left), offsetof(kbl_fr1d, right), offsetof(kbl_fr1d, limit));\n"
+        " return 0;}\n")
+    exe = tmp_path / "fr"
+    subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    vals = [int(x) for x in subprocess.check_output([str(exe)]).split()]
+    assert vals == [C.sizeof(L.Fr1dCfg), L.Fr1dCfg.n_elem.offset, L.Fr1dCfg.left.offset,
+                    L.Fr1dCfg.right.offset, L.Fr1dCfg.limit.offset]
+
+
+@pytest.mark.parametrize("kw", [dict(p=0), dict(p=8), dict(n_elem=1), dict(x1=0.0), dict(bc=5),
+                                dict(limit=2), dict(reserved=1)])
+def test_fr1d_rejects_bad_config(lib, kw):
+    c = _fr_cfg(**kw)
+    assert lib.kbl_fr1d_columns(C.byref(c)) == 0
+    assert lib.kbl_fr1d_workspace_bytes(C.byref(c)) == 0
+    assert lib.kbl_fr1d_rhs(C.byref(c), 1.4, FAKE, FAKE, None) == L.KBL_ERR_ARG
+    assert lib.kbl_fr1d_max_speed(C.byref(c), 1.4, FAKE, FAKE, None) == L.KBL_ERR_ARG
+
+
+def test_fr1d_sizes():
+    lib = L.lib()
+    c = _fr_cfg()
+    assert lib.kbl_fr1d_columns(C.byref(c)) == 16 * 6
+    d = _fr_cfg(bc=L.FR_DIRICHLET, left=(1, 0, 2.5), right=(0.125, 0, 0.25))
+    assert lib.kbl_fr1d_columns(C.byref(d)) == 18 * 6
+    assert lib.kbl_fr1d_workspace_bytes(C.byref(d)) >= 8 * 3 * 18 * 6 + 8 * 3 * 16 * 4 + 8 * 6 * 18
+
+
+def test_fr1d_step_and_limit_argument_errors(lib):
+    # every case returns before any launch (the pointers are fake)
+    p = _params(lib)
+    g = L.VGrid()
+    g.mode, g.n[0], g.k = L.GRID_STENCIL, 256, 8.0
+    c = _fr_cfg()
+    ws = lib.kbl_fr1d_workspace_bytes(C.byref(c))
+
+    def step(cfg=c, prm=p, grid=g, dt=1e-3, U=FAKE, wsb=ws):
+        return lib.kbl_fr1d_step(C.byref(cfg), C.byref(prm), C.byref(grid), dt, U, FAKE, wsb,
+                                 None, None)
+
+    def lim(cfg=c, prm=p, grid=g, U=FAKE, wsb=ws):
+        return lib.kbl_fr1d_limit(C.byref(cfg), C.byref(prm), C.byref(grid), U, FAKE, wsb, None, None)
+
+    for fn in (step, lim):
+        assert fn(wsb=ws - 1) == L.KBL_ERR_WORKSPACE
+        assert fn(U=None) == L.KBL_ERR_ARG
+        assert fn(prm=_params(lib, precision=L.PREC_MIXED_FP32)) == L.KBL_ERR_UNSUPPORTED
+        assert fn(prm=_params(lib, flags=L.FLAG_ENERGY_PERSTATE)) == L.KBL_ERR_UNSUPPORTED
+        assert fn(prm=_params(lib, gamma=1.0)) == L.KBL_ERR_GAMMA
+        bad = L.VGrid()
+        bad.mode, bad.n[0], bad.k = L.GRID_STENCIL, 5000, 8.0
+        assert fn(grid=bad) == L.KBL_ERR_GRID
+        dirich = _fr_cfg(bc=L.FR_DIRICHLET, left=(1.0, 0.0, -1.0), right=(0.125, 0.0, 0.25))
+        assert fn(cfg=dirich, wsb=lib.kbl_fr1d_workspace_bytes(C.byref(dirich))) == L.KBL_ERR_ARG
+    assert step(dt=0.0) == L.KBL_ERR_ARG
+    assert step(dt=float("nan")) == L.KBL_ERR_ARG

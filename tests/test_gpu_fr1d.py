@@ -1,0 +1,134 @@
+"""GPU 1D FR solver (include/kbl_fr1d.h) vs the plain FP64 reference solver
+(oracle/fr1d.py), through the C-ABI: the FR residual, the max wave speed, the
+limiting of a stage (bounds over the node stencils + squeeze limiter) and
+whole SSP-RK3 steps (bounds of each stage's input state, update, limiting:
+Sec. 3.9), periodic and Dirichlet, p = 1..7.
+
+Tolerances: residual 1e-12 of max|R|; the limited initial data 1e-12 of the
+element value scale; five limited steps 1e-10 (rounding differences pass
+through the limiter's decisions, which are continuous except at the epsilon
+rule).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import fr1d as ofr
+from synth import fr1d_problems as probs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def kbl():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2407_20966_amd as kbl
+    return kbl
+
+
+def smooth_states(rng, n, p, gamma=1.4):
+    rho = np.exp(rng.uniform(-1, 1, (n, 1))) * (1 + 0.05 * rng.uniform(-1, 1, (n, p + 1)))
+    u = rng.uniform(-1, 1, (n, 1)) + 0.05 * rng.uniform(-1, 1, (n, p + 1))
+    P = np.exp(rng.uniform(-1, 1, (n, 1))) * (1 + 0.05 * rng.uniform(-1, 1, (n, p + 1)))
+    return ofr.conserved(rho, u, P, gamma)
+
+
+def pair(kbl, p, n, x0, x1, gamma, bc="periodic", left=None, right=None, limit=True,
+         r_fac=1e-3, n_u=256):
+    g = kbl.FR1D(p, n, x0, x1, gamma, bc=bc, left=left, right=right, limit=limit, r_fac=r_fac,
+                 n_u=n_u, k=8.0)
+    o = ofr.FR1D(p, n, x0, x1, gamma, bc=bc, left=left, right=right)
+    return g, o
+
+
+def scale(U):
+    """Per (variable, element) value scale: max |U| over the element, momentum
+    floored by sqrt(rho E)."""
+    a = np.abs(U).max(2)
+    a[1] = np.maximum(a[1], np.sqrt(np.abs(U[0] * U[2])).max(1))
+    return a[:, :, None]
+
+
+@pytest.mark.parametrize("p", range(1, 8))
+@pytest.mark.parametrize("bc", ["periodic", "dirichlet"])
+def test_rhs_parity(kbl, p, bc):
+    rng = np.random.default_rng(100 + p)
+    n = 37
+    left = ofr.conserved(np.array(1.1), 0.2, 0.9, 1.4)
+    right = ofr.conserved(np.array(0.4), -0.1, 0.5, 1.4)
+    g, o = pair(kbl, p, n, 0.0, 1.3, 1.4, bc=bc, left=left, right=right, limit=False)
+    U = smooth_states(rng, n, p)
+    g.solution_view().copy_(torch.from_numpy(U))
+    R = g.rhs().cpu().numpy()
+    Ro = o.rhs(U)
+    err = np.abs(R - Ro).max() / np.abs(Ro).max()
+    print(f"[fr1d] rhs p={p} {bc}: rel err {err:.2e}", flush=True)
+    assert err <= 1e-12
+    sp = g.max_speed()
+    assert abs(sp - o.max_speed(U)) <= 1e-14 * sp
+
+
+@pytest.mark.parametrize("p", [2, 3, 5])
+@pytest.mark.parametrize("r_fac", [1e-3, 0.0])
+def test_initial_limiting_parity(kbl, p, r_fac):
+    # Sod data with the diaphragm at an element centre (odd n): the end values
+    # of that element overshoot to negative density; the initial limiting
+    # (bounds of the neighbouring solution points) brings them back
+    pr = probs.sod(p, 15)
+    g, o = pair(kbl, p, pr.n_elem, pr.x0, pr.x1, pr.gamma, bc="dirichlet", left=pr.left,
+                right=pr.right, r_fac=r_fac)
+    g.solution_view().copy_(torch.from_numpy(pr.U0))
+    g.limit()
+    torch.cuda.synchronize()
+    Ug = g.solution().cpu().numpy()
+    b, _ = o.bounds(pr.U0, n_u=256, k=8.0, r_fac=r_fac, initial=True)
+    Uo, alpha, lst = o.limit_into(pr.U0, b, return_info=True)
+    err = (np.abs(Ug - Uo) / scale(Uo)).max()
+    sg = g.status.cpu().numpy().view(np.uint32)
+    print(f"[fr1d] initial limit p={p} r={r_fac}: err {err:.2e}, limited "
+          f"{int((alpha[0] < 1).sum())}", flush=True)
+    assert (alpha[0] < 1).any()
+    assert err <= 1e-12
+    diff = sg != lst
+    if diff.any():
+        assert np.all(np.abs(alpha[0][diff] - 1.0) < 1e-9)
+    V = g.U.cpu().numpy().reshape(3, -1, p + 3)
+    assert (V[0] > 0).all() and (ofr.pressure(V, pr.gamma) > 0).all()
+
+
+@pytest.mark.parametrize("p,n,problem", [(3, 15, "sod"), (2, 21, "sod"), (4, 12, "pulse"),
+                                         (6, 9, "pulse")])
+def test_steps_parity(kbl, p, n, problem):
+    pr = probs.sod(p, n) if problem == "sod" else probs.pulse(p, n, sigma=100.0)
+    g, o = pair(kbl, p, n, pr.x0, pr.x1, pr.gamma, bc=pr.bc, left=pr.left, right=pr.right)
+    h = (pr.x1 - pr.x0) / n
+    # start from the limited initial data (its end values are then admissible)
+    U = o.limit_initial(pr.U0, n_u=256, k=8.0, r_fac=1e-3)
+    dt = 0.5 * h / ((2 * p + 1) * o.max_speed(U))
+    g.solution_view().copy_(torch.from_numpy(U))
+    for _ in range(5):
+        g.step(dt)
+        U = o.step(U, dt, n_u=256, k=8.0, r_fac=1e-3)
+    torch.cuda.synchronize()
+    Ug = g.solution().cpu().numpy()
+    err = (np.abs(Ug - U) / scale(U)).max()
+    print(f"[fr1d] 5 steps {problem} p={p} n={n}: err {err:.2e}", flush=True)
+    assert err <= 1e-10
+
+
+def test_conservation_and_positivity_over_many_steps(kbl):
+    # periodic: the limiter keeps element means, so totals stay put
+    p, n = 3, 40
+    pr = probs.pulse(p, n, sigma=2000.0)
+    g = kbl.FR1D(p, n, pr.x0, pr.x1, pr.gamma, n_u=512)
+    g.solution_view().copy_(torch.from_numpy(pr.U0))
+    w = np.polynomial.legendre.leggauss(p + 1)[1]
+    tot0 = (g.solution().cpu().numpy() @ w).sum(1)
+    steps = g.run(0.2, 0.5)
+    U = g.solution().cpu().numpy()
+    tot = (U @ w).sum(1)
+    print(f"[fr1d] {steps} steps: totals drift {np.abs(tot - tot0).max():.2e}", flush=True)
+    np.testing.assert_allclose(tot, tot0, rtol=1e-12, atol=1e-12)
+    assert (U[0] > 0).all() and (ofr.pressure(U, 1.4) > 0).all()
