@@ -26,9 +26,9 @@ definitions, slow and direct:
   values on the shared faces; the updated state is then limited (squeeze
   limiter and pressure step) over V = the element's solution points and end
   values, with zero mean weight on the end values (Sec. 5; the bounds and
-  limiter of Sec. 3 from the ``oracle`` package).  Initial data are limited
-  once into the bounds of the solution points of each element and its two
-  face neighbours.
+  limiter of Sec. 3 from the ``oracle`` package).  Initial data: elements
+  with a non-admissible node value are limited once into the bounds of the
+  solution points of the element and its two face neighbours.
 * Boundaries: periodic, or Dirichlet through constant ghost states on both
   sides (the common flux at a boundary face is the HLLC flux against the
   ghost state, and the ghost's end value joins the boundary element's
@@ -234,10 +234,17 @@ class FR1D:
 
     def limit_initial(self, U: np.ndarray, n_u: int = 2048, k: float = 8.0,
                       r_fac: float = 1e-3) -> np.ndarray:
-        """Initial data: limited once into the bounds of the solution points of
-        each element and its face neighbours (the end values of discontinuous
-        initial data need not be admissible)."""
+        """Initial data: an element whose polynomial has a non-admissible node
+        value (rho <= 0 or P <= 0 at a solution point or end value, as the
+        end values of discontinuous data can) is limited into the bounds of
+        the solution points of the element and its two face neighbours; every
+        other element is left as it is (NaN bounds pass it through)."""
         b, _ = self.bounds(U, n_u, k, r_fac, initial=True)
+        n_v, n_tot, _, _ = self.stencil_layout()
+        V = self.v_states(U).reshape(3, n_tot, n_v)
+        good = ((V[0] > 0) & (pressure(V, self.gamma) > 0)).all(1)
+        b = b.copy()
+        b[:, good] = np.nan
         return self.limit_into(U, b)
 
     # ------------------------------------------------------------- time
