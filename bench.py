@@ -341,6 +341,38 @@ def time_3d(args, kbl, torch, synth, stream):
     return out
 
 
+def time_fr1d(args, kbl, torch, stream):
+    """One SSP-RK3 step of the 1D FR solver with the kinetic bounds and limiter
+    after every stage (Sec. 5), on the paper's finest Sod mesh (p = 3,
+    N = 3200, velocity grid k = 8 with 2048 nodes)."""
+    from synth import fr1d_problems as probs
+    pr = probs.sod(3, 3200)
+    s = kbl.FR1D(pr.p, pr.n_elem, pr.x0, pr.x1, pr.gamma, bc=pr.bc, left=pr.left,
+                 right=pr.right, r_fac=1e-3, n_u=2048, k=8.0, stream=stream)
+    s.set_solution(pr.U0)
+    h = (pr.x1 - pr.x0) / pr.n_elem
+    dt = 0.1 * h / ((2 * pr.p + 1) * s.max_speed())
+    steps = max(20, 10 * args.steps)
+    ms = _time_events(torch, stream, lambda: s.step(dt), steps, max(2, args.warmup))
+    # the same with the CFL time step taken every step (one host sync each)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        sp = s.max_speed()
+        s.step(0.1 * h / ((2 * pr.p + 1) * sp))
+    torch.cuda.synchronize()
+    ms_cfl = 1e3 * (time.perf_counter() - t0) / steps
+    pairs = 3 * (pr.n_elem * (pr.p + 5) + 2 * (pr.p + 3)) * 2048
+    print(f"[bench] fr1d sod p=3 N=3200: {ms:.3f} ms/step ({ms_cfl:.3f} with the CFL sync)",
+          file=sys.stderr, flush=True)
+    return {"workload": "Sod shock tube, FR p=3, 3200 elements, HLLC, SSP-RK3 with the kinetic "
+                        "bounds (k=8, 2048 velocity nodes, node stencils of 10 states) and the "
+                        "squeeze limiter after every stage",
+            "ms_per_step": ms, "steps_per_s": 1e3 / ms, "ms_per_step_with_cfl_sync": ms_cfl,
+            "element_stages_per_s": 3 * pr.n_elem / (ms * 1e-3),
+            "bounds_pairs_per_step": pairs,
+            "launches_per_step": 14}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -352,6 +384,7 @@ def main(argv=None):
     ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
     ap.add_argument("--no-fr", action="store_true", help="skip the node-level stencil timing")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D velocity-grid timing")
+    ap.add_argument("--no-solver", action="store_true", help="skip the 1D FR solver step timing")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variant timings (energy reading, r = 0, independent "
                          "limiting, node-level stencils)")
@@ -555,6 +588,8 @@ def main(argv=None):
                                         ms_step, b_ms)
     if not args.no_3d and wl.dim == 2:
         out["three_d"] = time_3d(args, kbl, torch, synth, stream)
+    if not args.no_solver and wl.dim == 2:
+        out["fr1d_solver"] = time_fr1d(args, kbl, torch, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

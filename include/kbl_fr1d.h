@@ -74,13 +74,14 @@ kbl_status kbl_fr1d_rhs(const kbl_fr1d* cfg, double gamma, const double* U, doub
                         void* stream);
 
 /*
- * kbl_fr1d_limit - limiting of initial data: writes the end values and
- * ghosts of U from its solution points, takes the bounds over the solution
- * points of each element and its two face neighbours, and limits U into
- * them in place (solution points and end values).  The end values of
- * discontinuous initial data need not be admissible, so they stay out of
- * these stencils.  params and vgrid as for kbl_compute_bounds (d = 1; the
- * paper uses k = 8 and 2048 velocity nodes in 1D).  elem_status: out
+ * kbl_fr1d_limit - repair of initial data: writes the end values and ghosts
+ * of U from its solution points; an element whose polynomial has a
+ * non-admissible node value (rho <= 0 or P <= 0 at a solution point or end
+ * value, as the end values of discontinuous data can) is limited in place
+ * into the bounds of the solution points of the element and its two face
+ * neighbours.  Every other element is left unchanged (its status reads
+ * KBL_ST_BAD_BOUNDS).  params and vgrid as for kbl_compute_bounds (d = 1;
+ * the paper uses k = 8 and 2048 velocity nodes in 1D).  elem_status: out
  * [n_tot] limiter status or NULL.  Does nothing but the end values and
  * ghosts when cfg->limit is 0.
  */
@@ -105,6 +106,27 @@ kbl_status kbl_fr1d_step(const kbl_fr1d* cfg, const kbl_params* params, const kb
  */
 kbl_status kbl_fr1d_max_speed(const kbl_fr1d* cfg, double gamma, const double* U, double* out,
                               void* stream);
+
+/*
+ * kbl_fr1d_cfl_dt - the CFL time step in device memory, for runs with no
+ * host synchronisation per step (e.g. batches of steps captured in a HIP
+ * graph).  tdt: device (t, dt).  Reads t = tdt[0]; writes
+ * dt = min(cfl h / ((2p + 1) max(|u| + c)), t_end - t) (0 once t >= t_end)
+ * to tdt[1] and the time after the step to tdt[0] (exactly t_end on the
+ * last step).  Both become NaN when a solution point is not admissible.
+ */
+kbl_status kbl_fr1d_cfl_dt(const kbl_fr1d* cfg, double gamma, const double* U, double cfl,
+                           double t_end, double* tdt, void* stream);
+
+/*
+ * kbl_fr1d_step_dev - kbl_fr1d_step with dt read from device memory (tdt[1],
+ * as written by kbl_fr1d_cfl_dt) when the kernels run.  Enqueues the same
+ * work; allocates nothing and does not synchronise, so it can be captured.
+ */
+kbl_status kbl_fr1d_step_dev(const kbl_fr1d* cfg, const kbl_params* params,
+                             const kbl_vgrid* vgrid, const double* tdt, double* U,
+                             void* workspace, size_t workspace_bytes, uint32_t* elem_status,
+                             void* stream);
 
 #ifdef __cplusplus
 }

@@ -150,6 +150,11 @@ def _load():
         lib.kbl_fr1d_step.restype = C.c_int
         lib.kbl_fr1d_max_speed.argtypes = [F, C.c_double, P, P, P]
         lib.kbl_fr1d_max_speed.restype = C.c_int
+        lib.kbl_fr1d_cfl_dt.argtypes = [F, C.c_double, P, C.c_double, C.c_double, P, P]
+        lib.kbl_fr1d_cfl_dt.restype = C.c_int
+        lib.kbl_fr1d_step_dev.argtypes = [F, C.POINTER(Params), C.POINTER(VGrid), P, P, P,
+                                          C.c_size_t, P, P]
+        lib.kbl_fr1d_step_dev.restype = C.c_int
         _lib = lib
     return _lib
 

@@ -54,6 +54,7 @@ struct FrArgs {
     double gamma;
     double left[3], right[3];
     double a, b, dt;    // U <- a U0 + b (U + dt R)
+    const double* tdt;  // device (t, dt): dt read from tdt[1] when not null
     FrOps ops;
 };
 
@@ -195,6 +196,7 @@ __global__ __launch_bounds__(kThreadsFr) void fr1d_stage(FrArgs a) {
             for (int v = 0; v < 3; ++v) a.U[v * a.cols + c0 + j] = g[v];
         return;
     }
+    const double dt = a.tdt ? a.tdt[1] : a.dt;
     double u[3][NS];
 #pragma unroll
     for (int v = 0; v < 3; ++v)
@@ -206,7 +208,7 @@ __global__ __launch_bounds__(kThreadsFr) void fr1d_stage(FrArgs a) {
             if (a.b != 0.0) {
                 const double u0 = a.save_u0 ? x : a.U0[c];
                 if (a.save_u0) a.U0[c] = x;
-                nu = a.a * u0 + a.b * (x + a.dt * a.R[v * (a.n_elem * NS) + e * NS + j]);
+                nu = a.a * u0 + a.b * (x + dt * a.R[v * (a.n_elem * NS) + e * NS + j]);
             }
             u[v][j] = nu;
             a.U[c] = nu;
@@ -257,10 +259,34 @@ __global__ __launch_bounds__(kThreadsFr) void fr1d_csr(int64_t n_elem, int64_t n
     if (r == n_tot - 1) rowptr[n_tot] = (int32_t)(start + len);
 }
 
+// Initial limiting: elements whose n_v node values are all admissible keep
+// their data (NaN bounds: the limiter passes them through unchanged).
+__global__ __launch_bounds__(kThreadsFr) void fr1d_keep_admissible(const double* U, int64_t n_tot,
+                                                                   int64_t cols, int32_t n_v,
+                                                                   double gm1, double* bounds) {
+    const int64_t e = (int64_t)blockIdx.x * kThreadsFr + threadIdx.x;
+    if (e >= n_tot) return;
+    bool good = true;
+    for (int j = 0; j < n_v; ++j) {
+        const int64_t c = e * n_v + j;
+        const double r = U[c], m = U[cols + c], E = U[2 * cols + c];
+        const double P = gm1 * (E - 0.5 * m * m / r);
+        good = good && r > 0.0 && P > 0.0 && isfinite(r) && isfinite(P);
+    }
+    if (good) {
+        const double nan = __longlong_as_double(0x7ff8000000000000LL);
+        for (int v = 0; v < 6; ++v) bounds[v * n_tot + e] = nan;
+    }
+}
+
 // max |u| + c over the solution points; NaN when a point is not admissible.
+// With tdt (device (t, dt)): instead writes the CFL time step
+// dt = min(cfl_h / s, t_end - t) and advances t (NaN for both when a point
+// is not admissible).
 __global__ __launch_bounds__(1024) void fr1d_max_speed(const double* U, int64_t n_elem, int64_t cols,
                                                        int32_t n_v, int32_t ns, double gamma,
-                                                       double* out) {
+                                                       double* out, double* tdt, double cfl_h,
+                                                       double t_end) {
     __shared__ double red[1024];
     __shared__ int bad;
     if (threadIdx.x == 0) bad = 0;
@@ -283,7 +309,22 @@ __global__ __launch_bounds__(1024) void fr1d_max_speed(const double* U, int64_t 
         if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
         __syncthreads();
     }
-    if (threadIdx.x == 0) *out = bad ? __longlong_as_double(0x7ff8000000000000LL) : red[0];
+    if (threadIdx.x != 0) return;
+    const double nan = __longlong_as_double(0x7ff8000000000000LL);
+    if (!tdt) {
+        *out = bad ? nan : red[0];
+        return;
+    }
+    const double t = tdt[0];
+    double dt = cfl_h / red[0];
+    const double rem = t_end - t;
+    double tn;
+    if (!(rem > 0.0)) { dt = 0.0; tn = t; }
+    else if (dt >= rem) { dt = rem; tn = t_end; }
+    else tn = t + dt;
+    if (bad || !(red[0] > 0.0)) { dt = nan; tn = nan; }
+    tdt[0] = tn;
+    tdt[1] = dt;
 }
 
 // ------------------------------------------------------------ host side
@@ -544,15 +585,24 @@ kbl_status kbl_fr1d_limit(const kbl_fr1d* cfg, const kbl_params* params, const k
     if (kbl::launch_csr(a, ws, true, st) != hipSuccess) return KBL_ERR_HIP;
     rc = kbl::stencil_bounds(cfg, params, vgrid, a, ws, true, st);
     if (rc != KBL_OK) return rc;
+    hipLaunchKernelGGL(kbl::fr1d_keep_admissible, dim3(kbl::blocks_for(a.n_tot)),
+                       dim3(kbl::kThreadsFr), 0, st, a.U, a.n_tot, a.cols, a.n_v, a.gm1, ws.bounds);
+    if (hipGetLastError() != hipSuccess) return KBL_ERR_HIP;
     return kbl::limit_into(cfg, params, a, ws, w, elem_status, st);
 }
 
-kbl_status kbl_fr1d_step(const kbl_fr1d* cfg, const kbl_params* params, const kbl_vgrid* vgrid,
-                         double dt, double* U, void* workspace, size_t workspace_bytes,
-                         uint32_t* elem_status, void* stream) {
+}  // extern "C"
+
+namespace kbl {
+namespace {
+
+// One SSP-RK3 step; dt from the argument, or from tdt[1] in device memory.
+kbl_status step_impl(const kbl_fr1d* cfg, const kbl_params* params, const kbl_vgrid* vgrid,
+                     double dt, const double* tdt, double* U, void* workspace,
+                     size_t workspace_bytes, uint32_t* elem_status, void* stream) {
     kbl_status rc = kbl::check_limit_args(cfg, params, vgrid, U, workspace, workspace_bytes);
     if (rc != KBL_OK) return rc;
-    if (!(dt > 0.0) || !isfinite(dt)) return KBL_ERR_ARG;
+    if (!tdt && (!(dt > 0.0) || !isfinite(dt))) return KBL_ERR_ARG;
     kbl::FrArgs a;
     double w[kbl::kMaxNs];
     rc = kbl::make_args(cfg, params->gamma, U, &a, w);
@@ -563,6 +613,7 @@ kbl_status kbl_fr1d_step(const kbl_fr1d* cfg, const kbl_params* params, const kb
     a.U0 = ws.U0;
     a.R = ws.R;
     a.dt = dt;
+    a.tdt = tdt;
     if (cfg->limit) {
         if (kbl::launch_csr(a, ws, false, st) != hipSuccess) return KBL_ERR_HIP;
         // end values and ghosts of the input state (its bounds need them)
@@ -593,12 +644,47 @@ kbl_status kbl_fr1d_step(const kbl_fr1d* cfg, const kbl_params* params, const kb
     return KBL_OK;
 }
 
+}  // namespace
+}  // namespace kbl
+
+extern "C" {
+
+kbl_status kbl_fr1d_step(const kbl_fr1d* cfg, const kbl_params* params, const kbl_vgrid* vgrid,
+                         double dt, double* U, void* workspace, size_t workspace_bytes,
+                         uint32_t* elem_status, void* stream) {
+    return kbl::step_impl(cfg, params, vgrid, dt, nullptr, U, workspace, workspace_bytes,
+                          elem_status, stream);
+}
+
+kbl_status kbl_fr1d_step_dev(const kbl_fr1d* cfg, const kbl_params* params,
+                             const kbl_vgrid* vgrid, const double* tdt, double* U,
+                             void* workspace, size_t workspace_bytes, uint32_t* elem_status,
+                             void* stream) {
+    if (!tdt) return KBL_ERR_ARG;
+    return kbl::step_impl(cfg, params, vgrid, 0.0, tdt, U, workspace, workspace_bytes,
+                          elem_status, stream);
+}
+
 kbl_status kbl_fr1d_max_speed(const kbl_fr1d* cfg, double gamma, const double* U, double* out,
                               void* stream) {
     if (!kbl::valid_cfg(cfg) || !U || !out || !(gamma > 1.0)) return KBL_ERR_ARG;
     const int64_t nt = kbl::n_total(cfg);
     hipLaunchKernelGGL(kbl::fr1d_max_speed, dim3(1), dim3(1024), 0, (hipStream_t)stream, U,
-                       cfg->n_elem, nt * (cfg->p + 3), cfg->p + 3, cfg->p + 1, gamma, out);
+                       cfg->n_elem, nt * (cfg->p + 3), cfg->p + 3, cfg->p + 1, gamma, out,
+                       nullptr, 0.0, 0.0);
+    return hipGetLastError() == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
+kbl_status kbl_fr1d_cfl_dt(const kbl_fr1d* cfg, double gamma, const double* U, double cfl,
+                           double t_end, double* tdt, void* stream) {
+    if (!kbl::valid_cfg(cfg) || !U || !tdt || !(gamma > 1.0) || !(cfl > 0.0) || !isfinite(cfl) ||
+        !isfinite(t_end))
+        return KBL_ERR_ARG;
+    const int64_t nt = kbl::n_total(cfg);
+    const double h = (cfg->x1 - cfg->x0) / (double)cfg->n_elem;
+    hipLaunchKernelGGL(kbl::fr1d_max_speed, dim3(1), dim3(1024), 0, (hipStream_t)stream, U,
+                       cfg->n_elem, nt * (cfg->p + 3), cfg->p + 3, cfg->p + 1, gamma, nullptr, tdt,
+                       cfl * h / (2.0 * cfg->p + 1.0), t_end);
     return hipGetLastError() == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 

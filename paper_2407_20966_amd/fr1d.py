@@ -108,6 +108,51 @@ class FR1D:
                     "kbl_fr1d_max_speed")
         return float(self._speed.item())
 
+    def _device_step(self, tdt: torch.Tensor, cfl: float, t_end: float, stream) -> None:
+        lib = L.lib()
+        sp = C.c_void_p(stream.cuda_stream)
+        self._check(lib.kbl_fr1d_cfl_dt(C.byref(self.cfg), self.gamma,
+                                        C.c_void_p(self.U.data_ptr()), float(cfl), float(t_end),
+                                        C.c_void_p(tdt.data_ptr()), sp), "kbl_fr1d_cfl_dt")
+        self._check(lib.kbl_fr1d_step_dev(C.byref(self.cfg), C.byref(self.params),
+                                          C.byref(self.vgrid), C.c_void_p(tdt.data_ptr()),
+                                          C.c_void_p(self.U.data_ptr()),
+                                          C.c_void_p(self.ws.data_ptr()), self.ws.numel(),
+                                          C.c_void_p(self.status.data_ptr()), sp),
+                    "kbl_fr1d_step_dev")
+
+    def run_device(self, t_end: float, cfl: float, batch: int = 0,
+                   max_steps: int = 10_000_000) -> int:
+        """As run(), with the time step computed on the device (no host sync
+        per step).  batch > 0: batches of that many steps are captured once
+        in a HIP graph and replayed while the end time is more than two
+        batches away; the remaining steps run one by one.  Returns the
+        number of steps."""
+        tdt = torch.zeros(2, dtype=torch.float64, device=self.device)
+        graph = None
+        if batch > 0:
+            graph = torch.cuda.CUDAGraph()
+            side = torch.cuda.Stream(self.device)
+            side.wait_stream(self.stream)
+            with torch.cuda.graph(graph, stream=side):
+                for _ in range(batch):
+                    self._device_step(tdt, cfl, t_end, side)
+            self.stream.wait_stream(side)
+        n = 0
+        while n < max_steps:
+            t, dt = (float(v) for v in tdt.tolist())
+            if not (t == t and dt == dt):
+                raise FloatingPointError(f"non-admissible state after {n} steps")
+            if t >= t_end:
+                break
+            if graph is not None and n > 0 and t + 2.0 * batch * dt < t_end:
+                graph.replay()
+                n += batch
+            else:
+                self._device_step(tdt, cfl, t_end, self.stream)
+                n += 1
+        return n
+
     def run(self, t_end: float, cfl: float, max_steps: int = 10_000_000) -> int:
         """Steps to t_end with dt = cfl * h / ((2p + 1) max|u| + c).
         Returns the number of steps; raises if the state stops being admissible."""

@@ -1,0 +1,107 @@
+"""The error tables of Sec. 6, reproduced with the GPU FR solver (kbl_fr1d.h)
+and compared with the values the paper prints (tests/golden/fr1d_tables.json).
+
+Protocol (the paper gives neither): dt = 0.1 h / ((2p + 1) max(|u| + c)),
+velocity grid k = 8 with 2048 nodes (Sec. 5), r = 1e-3 (relaxed) or 0
+(strict).  The pulse uses sigma = 200: the paper's table matches that value,
+not the sigma = 500 of its text (pinned on the CPU in test_oracle_fr1d.py).
+
+Bars: pulse within 3% (p <= 3) or 20% (p = 4, 5) of the printed L_inf errors,
+with limited and unlimited errors equal to 1% (the limiter leaves smooth
+extrema alone, with strict bounds too); Sod within [0.55, 1.3] of the printed
+L1 errors for N >= 50 with rates between 0.75 and 1.25; Leblanc positive
+throughout and within a factor of 4 of the printed errors.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import exact_riemann as ER
+from synth import fr1d_problems as probs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+CFL = 0.1
+G = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "fr1d_tables.json")))
+
+
+@pytest.fixture(scope="module")
+def kbl():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    import paper_2407_20966_amd as kbl
+    return kbl
+
+
+def solve(kbl, pr, r_fac, limit=True):
+    s = kbl.FR1D(pr.p, pr.n_elem, pr.x0, pr.x1, pr.gamma, bc=pr.bc, left=pr.left,
+                 right=pr.right, r_fac=r_fac, n_u=2048, k=8.0, limit=limit)
+    s.set_solution(pr.U0)
+    steps = s.run(pr.t_end, CFL)
+    return s.solution().cpu().numpy(), steps
+
+
+@pytest.mark.parametrize("which", ["relaxed", "strict"])
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_pulse_table(kbl, which, p):
+    r = 1e-3 if which == "relaxed" else 0.0
+    for i, n in ((0, 10), (2, 20)):
+        pr = probs.pulse(p, n, sigma=200.0)
+        exact = probs.pulse(p, n, sigma=200.0, t=1.0).U0[0]
+        U, steps = solve(kbl, pr, r)
+        e = np.abs(U[0] - exact).max()
+        Uu, _ = solve(kbl, pr, r, limit=False)
+        eu = np.abs(Uu[0] - exact).max()
+        ref = G["pulse"][which][str(p)][i]
+        print(f"[table] pulse {which} p={p} N={n}: {e:.4e} (unlimited {eu:.4e}, paper {ref:.4e}, "
+              f"ratio {e / ref:.3f}, {steps} steps)", flush=True)
+        assert abs(e / eu - 1.0) < 0.01
+        tol = 0.03 if p <= 3 else 0.20
+        assert abs(e / ref - 1.0) < tol
+
+
+def sod_error(kbl, p, n, r):
+    pr = probs.sod(p, n)
+    U, steps = solve(kbl, pr, r)
+    WL, WR, xd = pr.riemann
+    rho, _, _ = ER.solution(WL, WR, pr.gamma, pr.x, pr.t_end, xd)
+    return np.abs(U[0] - rho).mean(), steps
+
+
+@pytest.mark.parametrize("which", ["relaxed", "strict"])
+@pytest.mark.parametrize("p", [2, 3])
+def test_sod_table(kbl, which, p):
+    r = 1e-3 if which == "relaxed" else 0.0
+    errs = []
+    for i, n in enumerate(G["sod"]["N"][:4]):
+        e, steps = sod_error(kbl, p, n, r)
+        ref = G["sod"][which][str(p)][i]
+        print(f"[table] sod {which} p={p} N={n}: {e:.4e} (paper {ref:.4e}, ratio {e / ref:.3f}, "
+              f"{steps} steps)", flush=True)
+        lo, hi = (0.9, 1.9) if n == 25 else (0.55, 1.3)
+        assert lo <= e / ref <= hi
+        errs.append(e)
+    rates = np.log2(np.array(errs[1:-1]) / np.array(errs[2:]))
+    print(f"[table] sod {which} p={p} rates N=50..200: {np.round(rates, 3)}", flush=True)
+    assert np.all((rates > 0.75) & (rates < 1.25))
+
+
+def test_leblanc_table(kbl):
+    for i, n in enumerate(G["leblanc"]["N"][:2]):
+        pr = probs.leblanc(3, n)
+        U, steps = solve(kbl, pr, 1e-3)
+        g = pr.gamma
+        rho, m, E = U
+        P = (g - 1) * (E - 0.5 * m * m / rho)
+        assert (rho > 0).all() and (P > 0).all()
+        WL, WR, xd = pr.riemann
+        re, ue, Pe = ER.solution(WL, WR, g, pr.x, pr.t_end, xd)
+        e = np.abs(rho - re).mean()
+        ref = G["leblanc"]["relaxed"]["rho"][i]
+        print(f"[table] leblanc p=3 N={n}: rho {e:.4e} (paper {ref:.4e}, ratio {e / ref:.3f}, "
+              f"{steps} steps)", flush=True)
+        assert 0.25 <= e / ref <= 4.0
