@@ -163,31 +163,40 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
             }
         }
 
-        // exp, relaxation, trapezoid weights and the moment contraction
+        // exp, relaxation, trapezoid weights and the moment contraction.  The
+        // node coordinates and weights are formed here from box values passed
+        // through an empty asm statement: otherwise the compiler computes
+        // them (and other element-invariant parts of this contraction) before
+        // the hot loop and keeps them live across it (register pressure).
+        double cx = lox, cy = loy, dx = hx, dy = hy;
+        int otx = tx, oty = ty;
+        asm volatile("" : "+v"(cx), "+v"(cy), "+v"(dx), "+v"(dy), "+v"(otx), "+v"(oty));
         double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
-            const int jx = tx + BX * i;
+            const int jx = otx + BX * i;
             if (jx >= p.nx) continue;
-            const double wx = hx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+            const double vx = node_pos(cx, jx, dx);
+            const double wx = dx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
-                const int jy = ty + BY * j;
+                const int jy = oty + BY * j;
                 if (jy >= p.ny) continue;
-                const double M = wx * (hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
+                const double vy = node_pos(cy, jy, dy);
+                const double M = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
                 const double ftn = rm * exp(qtn[i][j]);
                 const double ftx = rp * exp(qtx[i][j]);
                 const double fin = rm * exp(qin[i][j]);
                 const double fix = rp * exp(qix[i][j]);
-                const double hu2 = 0.5 * ux[i] * ux[i] + 0.5 * uy[j] * uy[j];
+                const double hu2 = 0.5 * vx * vx + 0.5 * vy * vy;
                 part[0] += M * ftn;
                 part[1] += M * ftx;
                 part[2] += M * (hu2 * ftn + fin);
                 part[3] += M * (hu2 * ftx + fix);
-                if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
-                else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
-                if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
-                else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
+                if (vx < 0.0) { part[4] += M * vx * ftx; part[5] += M * vx * ftn; }
+                else          { part[4] += M * vx * ftn; part[5] += M * vx * ftx; }
+                if (vy < 0.0) { part[6] += M * vy * ftx; part[7] += M * vy * ftn; }
+                else          { part[6] += M * vy * ftn; part[7] += M * vy * ftx; }
                 // one node at a time: keeps the exp temporaries of different
                 // nodes from being interleaved (register pressure)
                 __builtin_amdgcn_sched_barrier(0);

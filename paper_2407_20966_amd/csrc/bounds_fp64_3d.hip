@@ -84,29 +84,35 @@ __global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
                 if (c0 > 0 || (z0 > 0 && S > kMaxStates)) stage_chunk<3, NT>(p, row0, c0, cn, sC);
                 for (int t0 = 0; t0 < cn; t0 += kTab) {
                     const int tn = (cn - t0) < kTab ? (cn - t0) : kTab;
+                    // table builds from opaque copies of the box (keeps their
+                    // loop-invariant parts from being held across the hot loop)
+                    double bx0 = lox, by0 = loy, bz0 = loz, bhx = hx, bhy = hy, bhz = hz;
+                    int otid = tid;
+                    asm volatile("" : "+v"(bx0), "+v"(by0), "+v"(bz0), "+v"(bhx), "+v"(bhy),
+                                 "+v"(bhz), "+v"(otid));
                     __syncthreads();
-                    for (int idx = tid; idx < tn * NXM; idx += NT) {
+                    for (int idx = otid; idx < tn * NXM; idx += NT) {
                         const int s = idx / NXM, i = idx - s * NXM;
                         const int ic = i < p.nx ? i : p.nx - 1;
                         const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(lox, ic, hx) - c.ux;
+                        const double d = node_pos(bx0, ic, bhx) - c.ux;
                         sA[s][i] = fma(c.nk * d, d, c.a);
                     }
-                    for (int idx = tid; idx < tn * NYM; idx += NT) {
+                    for (int idx = otid; idx < tn * NYM; idx += NT) {
                         const int s = idx / NYM, j = idx - s * NYM;
                         const int jc = j < p.ny ? j : p.ny - 1;
                         const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(loy, jc, hy) - c.uy;
+                        const double d = node_pos(by0, jc, bhy) - c.uy;
                         sB[s][j] = (c.nk * d) * d;
                     }
-                    for (int idx = tid; idx < tn * NZP; idx += NT) {
+                    for (int idx = otid; idx < tn * NZP; idx += NT) {
                         const int s = idx / NZP, k = idx - s * NZP;
                         const int jz = z0 + k < p.nz ? z0 + k : p.nz - 1;
                         const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(loz, jz, hz) - c.uz;
+                        const double d = node_pos(bz0, jz, bhz) - c.uz;
                         sZ[s][k] = (c.nk * d) * d;
                     }
-                    for (int s = tid; s < tn; s += NT) sL[s] = sC[t0 + s].al - sC[t0 + s].a;
+                    for (int s = otid; s < tn; s += NT) sL[s] = sC[t0 + s].al - sC[t0 + s].a;
                     __syncthreads();
 #pragma unroll 2
                     for (int s = 0; s < tn; ++s) {
@@ -147,28 +153,30 @@ __global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
             // slab-invariant part of this contraction out of the slab loop and
             // keeps it live across the hot loop (register pressure).
             double cx = lox, cy = loy, cz = loz, dx = hx, dy = hy, dz = hz;
-            asm volatile("" : "+v"(cx), "+v"(cy), "+v"(cz), "+v"(dx), "+v"(dy), "+v"(dz));
+            int otx = tx, oty = ty, otz = tz;
+            asm volatile("" : "+v"(cx), "+v"(cy), "+v"(cz), "+v"(dx), "+v"(dy), "+v"(dz),
+                         "+v"(otx), "+v"(oty), "+v"(otz));
             double ux[TX], uy[TY], uz[TZ];
 #pragma unroll
-            for (int i = 0; i < TX; ++i) ux[i] = node_pos(cx, tx + BX * i, dx);
+            for (int i = 0; i < TX; ++i) ux[i] = node_pos(cx, otx + BX * i, dx);
 #pragma unroll
-            for (int j = 0; j < TY; ++j) uy[j] = node_pos(cy, ty + BY * j, dy);
+            for (int j = 0; j < TY; ++j) uy[j] = node_pos(cy, oty + BY * j, dy);
 #pragma unroll
-            for (int k = 0; k < TZ; ++k) uz[k] = node_pos(cz, z0 + tz + BZ * k, dz);
+            for (int k = 0; k < TZ; ++k) uz[k] = node_pos(cz, z0 + otz + BZ * k, dz);
             double part[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
             for (int i = 0; i < TX; ++i) {
-                const int jx = tx + BX * i;
+                const int jx = otx + BX * i;
                 if (jx >= p.nx) continue;
                 const double wx = dx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
-                    const int jy = ty + BY * j;
+                    const int jy = oty + BY * j;
                     if (jy >= p.ny) continue;
                     const double wxy = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
 #pragma unroll
                     for (int k = 0; k < TZ; ++k) {
-                        const int jz = z0 + tz + BZ * k;
+                        const int jz = z0 + otz + BZ * k;
                         if (jz >= p.nz) continue;
                         const double M = wxy * (dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0));
                         const double ftn = rm * exp(qtn[i][j][k]);
@@ -241,13 +249,14 @@ bool bounds_tile_fits_3d(int tile, int nx, int ny, int nz) {
     return nx <= t.bx * t.tx && ny <= t.by * t.ty;
 }
 
-// Defaults: the largest thread tile that still allows two waves per SIMD
-// (about nine nodes per thread); kbl_autotune_bounds may pick another.
+// Defaults: a thread tile that keeps two waves per SIMD (up to 18 nodes per
+// thread; at 24^3 the 3 x 3 x 2 tile measured fastest); kbl_autotune_bounds
+// may pick another.
 int bounds_default_tile_3d(int nx, int ny, int nz) {
     (void)nz;
     const int n = nx > ny ? nx : ny;
     if (n <= 16) return 0;
-    if (n <= 24) return 1;
+    if (n <= 24) return 6;
     if (n <= 32) return 2;
     if (n <= 48) return 3;
     return 4;
