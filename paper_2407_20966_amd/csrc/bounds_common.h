@@ -8,6 +8,7 @@
 #include <math.h>
 
 #include "kbl_internal.h"
+#include "exp2_table.h"
 
 namespace kbl {
 namespace {
@@ -152,6 +153,42 @@ __device__ __forceinline__ double box_hi(double u, double k, double sd) {
 #pragma clang fp contract(off)
     return u + k * sd;
 }
+// exp for the moment contraction, by Tang's table-driven method (ACM TOMS
+// 15(2), 1989): x = (256 m + j) ln(2)/256 + r with |r| <= ln(2)/512, so that
+// exp(x) = 2^m 2^(j/256) exp(r).  exp(r) - 1 is its degree-4 Taylor
+// polynomial (remainder below 4e-17), evaluated as
+// r (24 + r (12 + r (4 + r))) / 24 with the 1/24 taken from the table
+// (T/24 next to T): every constant then fits the one scalar operand an
+// instruction may read.  r is reduced with ln(2)/256 in two parts.  Error
+// about 1 ulp.  The argument is clamped below at -1100 (-inf gives 0); the
+// callers' arguments are bounded above by the log-peaks of admissible states.
+// 14 VALU ops and one LDS read, against 22 VALU ops of the general-purpose
+// exp.  tab: the table staged in LDS by stage_exp_table (a global table read
+// per lane waits on memory latency).
+__device__ __forceinline__ double exp_tab(double x, const ExpPair* tab) {
+    constexpr double kInvStep = 0x1.71547652b82fep+8;   // 256 / ln 2
+    // the empty asm keeps the clamp at the use; otherwise the compiler
+    // clamps every accumulator of the caller at once (register pressure)
+    asm volatile("" : "+v"(x));
+    x = fmax(x, -1100.0);
+    const double n = rint(x * kInvStep);
+    const int ni = (int)n;
+    double r = fma(-n, kLn2By256Hi, x);
+    r = fma(-n, kLn2By256Lo, r);
+    double q = r + 4.0;
+    q = fma(r, q, 12.0);
+    q = fma(r, q, 24.0);
+    q = r * q;
+    const ExpPair T = tab[ni & 255];
+    return ldexp(fma(T.t24, q, T.t), ni >> 8);
+}
+
+// Copies the exp table into LDS; the caller's next barrier publishes it.
+template <int NT>
+__device__ __forceinline__ void stage_exp_table(ExpPair* tab) {
+    for (int i = threadIdx.x; i < 256; i += NT) tab[i] = kExp2Tab[i];
+}
+
 // Velocity node j of a trapezoid grid starting at lo with spacing h.
 __device__ __forceinline__ double node_pos(double lo, int j, double h) {
 #pragma clang fp contract(off)

@@ -43,15 +43,18 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
     constexpr int NYM = BY * TY;
     constexpr int kTabStates = 32;
     static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    static_assert(BTAB == 0 || (NXM == NYM && NYM <= NT), "table tiles are square");
     __shared__ Coef sC[kMaxStates];
     __shared__ double sB[BTAB ? kTabStates : 1][BTAB ? NYM : 1];
     // BTAB = 2: A and A + l tables too (row 2s: A, row 2s+1: A + l)
     __shared__ double sA[BTAB == 2 ? 2 * kTabStates : 1][BTAB == 2 ? NXM : 1];
+    __shared__ ExpPair sExp[256];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = tid / BX;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
     for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
@@ -98,22 +101,29 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
             for (int t0 = 0; t0 < cn; t0 += (BTAB ? kTabStates : kMaxStates)) {
                 const int tn = BTAB ? ((cn - t0) < kTabStates ? (cn - t0) : kTabStates) : cn;
                 if (BTAB) {
+                    // Table columns: thread t fills node t % NYM of states
+                    // t / NYM, t / NYM + NT / NYM, ... (one node coordinate
+                    // per thread, no index arithmetic per entry).  The thread
+                    // index goes through an empty asm statement so that the
+                    // column and its coordinate are formed here, not kept
+                    // live across the hot loop.
+                    int ot = tid;
+                    asm volatile("" : "+v"(ot));
+                    const int j = ot % NYM, sj = ot / NYM;
+                    const double yj = node_pos(loy, j < p.ny ? j : p.ny - 1, hy);
+                    const double xj = node_pos(lox, j < p.nx ? j : p.nx - 1, hx);
                     __syncthreads();
-                    for (int idx = tid; idx < tn * NYM; idx += NT) {
-                        const int s = idx / NYM, j = idx - s * NYM;
-                        const int jc = j < p.ny ? j : p.ny - 1;
-                        const double d = node_pos(loy, jc, hy) - sC[t0 + s].uy;
-                        sB[s][j] = (sC[t0 + s].nk * d) * d;
-                    }
-                    if (BTAB == 2) {
-                        for (int idx = tid; idx < tn * NXM; idx += NT) {
-                            const int s = idx / NXM, i = idx - s * NXM;
-                            const int ic = i < p.nx ? i : p.nx - 1;
-                            const Coef& c = sC[t0 + s];
-                            const double d = node_pos(lox, ic, hx) - c.ux;
-                            const double t = c.nk * d;
-                            sA[2 * s][i] = fma(t, d, c.a);
-                            sA[2 * s + 1][i] = fma(t, d, c.al);
+                    if (sj < NT / NYM) {
+                        for (int s = sj; s < tn; s += NT / NYM) {
+                            const Coef c = sC[t0 + s];
+                            const double d = yj - c.uy;
+                            sB[s][j] = (c.nk * d) * d;
+                            if (BTAB == 2) {
+                                const double dx = xj - c.ux;
+                                const double t = c.nk * dx;
+                                sA[2 * s][j] = fma(t, dx, c.a);
+                                sA[2 * s + 1][j] = fma(t, dx, c.al);
+                            }
                         }
                     }
                     __syncthreads();
@@ -168,10 +178,18 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
         // through an empty asm statement: otherwise the compiler computes
         // them (and other element-invariant parts of this contraction) before
         // the hot loop and keeps them live across it (register pressure).
+        // The sums run over the unrelaxed envelopes g = exp(q); the factors
+        // (1 -+ r) of eq. relaxed are applied once per thread afterwards.
+        // Momentum (eq. mmbounds, mpbounds): the lower bound takes the upper
+        // envelope where u < 0 and the lower one where u >= 0 (the upper
+        // bound the reverse), so M u is split by sign into min(M u, 0) and
+        // max(M u, 0), which feed separate sums without selects.
         double cx = lox, cy = loy, dx = hx, dy = hy;
         int otx = tx, oty = ty;
         asm volatile("" : "+v"(cx), "+v"(cy), "+v"(dx), "+v"(dy), "+v"(otx), "+v"(oty));
-        double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        double sr[2] = {0, 0}, se[2] = {0, 0};    // rho, E: (lower, upper) envelope sums
+        double mn[2][2] = {{0, 0}, {0, 0}};       // [dir][0]: sum u<0 of M u g_max, [1]: u>=0, M u g_min
+        double mx[2][2] = {{0, 0}, {0, 0}};       // [dir][0]: sum u<0 of M u g_min, [1]: u>=0, M u g_max
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int jx = otx + BX * i;
@@ -184,24 +202,32 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
                 if (jy >= p.ny) continue;
                 const double vy = node_pos(cy, jy, dy);
                 const double M = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
-                const double ftn = rm * exp(qtn[i][j]);
-                const double ftx = rp * exp(qtx[i][j]);
-                const double fin = rm * exp(qin[i][j]);
-                const double fix = rp * exp(qix[i][j]);
+                const double gtn = exp_tab(qtn[i][j], sExp);
+                const double gtx = exp_tab(qtx[i][j], sExp);
+                const double gin = exp_tab(qin[i][j], sExp);
+                const double gix = exp_tab(qix[i][j], sExp);
                 const double hu2 = 0.5 * vx * vx + 0.5 * vy * vy;
-                part[0] += M * ftn;
-                part[1] += M * ftx;
-                part[2] += M * (hu2 * ftn + fin);
-                part[3] += M * (hu2 * ftx + fix);
-                if (vx < 0.0) { part[4] += M * vx * ftx; part[5] += M * vx * ftn; }
-                else          { part[4] += M * vx * ftn; part[5] += M * vx * ftx; }
-                if (vy < 0.0) { part[6] += M * vy * ftx; part[7] += M * vy * ftn; }
-                else          { part[6] += M * vy * ftn; part[7] += M * vy * ftx; }
+                sr[0] += M * gtn;
+                sr[1] += M * gtx;
+                se[0] += M * (hu2 * gtn + gin);
+                se[1] += M * (hu2 * gtx + gix);
+                const double mu[2] = {M * vx, M * vy};
+#pragma unroll
+                for (int d = 0; d < 2; ++d) {
+                    const double neg = fmin(mu[d], 0.0), pos = fmax(mu[d], 0.0);
+                    mn[d][0] += neg * gtx;
+                    mn[d][1] += pos * gtn;
+                    mx[d][0] += neg * gtn;
+                    mx[d][1] += pos * gtx;
+                }
                 // one node at a time: keeps the exp temporaries of different
                 // nodes from being interleaved (register pressure)
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
+        double part[8] = {rm * sr[0], rp * sr[1], rm * se[0], rp * se[1],
+                          rp * mn[0][0] + rm * mn[0][1], rm * mx[0][0] + rp * mx[0][1],
+                          rp * mn[1][0] + rm * mn[1][1], rm * mx[1][0] + rp * mx[1][1]};
         block_sum<NT, 8>(part, red);
         if (tid == 0) store_bounds<2>(p, e, part, flags);
     }
@@ -420,9 +446,11 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
 template <int NT, int T>
 __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
     __shared__ Coef sC[kMaxStates];
+    __shared__ ExpPair sExp[256];
     __shared__ Red red;
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    stage_exp_table<NT>(sExp);   // published by the prologue's barriers
     for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
@@ -470,10 +498,10 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
             const int j = tid + NT * i;
             if (j >= p.nx) continue;
             const double M = h * ((j == 0 || j == p.nx - 1) ? 0.5 : 1.0);
-            const double ftn = rm * exp(qtn[i]);
-            const double ftx = rp * exp(qtx[i]);
-            const double fin = rm * exp(qin[i]);
-            const double fix = rp * exp(qix[i]);
+                        const double ftn = rm * exp_tab(qtn[i], sExp);
+            const double ftx = rp * exp_tab(qtx[i], sExp);
+            const double fin = rm * exp_tab(qin[i], sExp);
+            const double fix = rp * exp_tab(qix[i], sExp);
             const double hu2 = 0.5 * u[i] * u[i];
             part[0] += M * ftn;
             part[1] += M * ftx;
