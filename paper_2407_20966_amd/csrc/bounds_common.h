@@ -70,6 +70,7 @@ constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;   // row_half_mirror
 constexpr int kDppMirror = 0x140;       // row_mirror
+constexpr int kDppRor8 = 0x128;         // row_ror:8 (lane i <-> lane i ^ 8 in a row)
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_f64(double v) {
@@ -347,6 +348,22 @@ __device__ __forceinline__ void store_bounds(const BoundsArgs& p, int64_t e, con
     if (p.status) p.status[e] = flags;
 }
 
+// One of the 2 (D + 2) sums, in the order of store_bounds, stored by its
+// own thread; thread t == 0 (rho_min) applies the floor and writes the status.
+template <int D>
+__device__ __forceinline__ void store_bound_value(const BoundsArgs& p, int64_t e, int t, double v,
+                                                  uint32_t flags) {
+    const int nv = D + 2;
+    int row;
+    if (t < 4) row = (t & 1) * nv + (t >> 1) * (D + 1);
+    else row = ((t - 4) & 1) * nv + 1 + ((t - 4) >> 1);
+    if (t == 0) {
+        if (v < p.rho_floor) { v = p.rho_floor; flags |= KBL_ST_RHO_FLOOR; }
+        if (p.status) p.status[e] = flags;
+    }
+    p.bounds[(int64_t)row * p.n_elem + e] = v;
+}
+
 template <int D>
 __device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32_t flags) {
     // quiet NaN by its bit pattern (these translation units assume no NaN
@@ -354,6 +371,68 @@ __device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32
     const double nan = __longlong_as_double(0x7ff8000000000000LL);
     for (int v = 0; v < 2 * (D + 2); ++v) p.bounds[(int64_t)v * p.n_elem + e] = nan;
     if (p.status) p.status[e] = flags;
+}
+
+// Lane swaps of gfx950 on doubles, one 32-bit half at a time.  ROW16 false
+// (v_permlane32_swap): lanes 32-63 of a <-> lanes 0-31 of b.  ROW16 true
+// (v_permlane16_swap): odd rows of a <-> even rows of b (rows of 16 lanes).
+template <bool ROW16>
+__device__ __forceinline__ void lane_swap(double& a, double& b) {
+    const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+    const unsigned alo = (unsigned)ia, ahi = (unsigned)(ia >> 32);
+    const unsigned blo = (unsigned)ib, bhi = (unsigned)(ib >> 32);
+    const auto lo = ROW16 ? __builtin_amdgcn_permlane16_swap(alo, blo, false, false)
+                          : __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = ROW16 ? __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false)
+                          : __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+}
+
+// Fixed-order workgroup sum of 8 partials by transposition: each exchange
+// stage halves the number of values a lane carries, so a wave spends about
+// 40 VALU ops where eight separate wave sums spend about 200.
+//  1. v[k] and v[k + 4] exchange half-waves: lanes 0-31 then carry values
+//     0-3 summed over lanes l and l + 32, lanes 32-63 values 4-7.
+//  2. v[0] and v[2], v[1] and v[3] exchange rows: row r of v[0] carries
+//     value 2r, of v[1] value 2r + 1, each summed over 4 rows' worth.
+//  3. Within a row, lanes 0-7 keep v[0] and lanes 8-15 v[1] (exchange over
+//     lane bit 3), then bits 0-2 are summed on the DPP network: lane l then
+//     holds value l / 8 over the whole wave.
+//  4. Lanes 0, 8, ..., 56 publish their sums; thread t < 8 adds the waves'
+//     sums of value t in wave order.
+// All 64 lanes of every wave must be active.  Returns value t in thread
+// t < 8 (0 elsewhere).  Contains the barriers.
+template <int NT>
+__device__ __forceinline__ double block_sum8(double* v, Red& red) {
+    constexpr int NW = NT / 64;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lane_swap<false>(v[k], v[k + 4]);
+        v[k] += v[k + 4];
+    }
+    lane_swap<true>(v[0], v[2]);
+    v[0] += v[2];
+    lane_swap<true>(v[1], v[3]);
+    v[1] += v[3];
+    const bool upper = (lane & 8) != 0;
+    double y = upper ? v[1] : v[0];
+    const double give = upper ? v[0] : v[1];
+    y += dpp_f64<kDppRor8>(give);
+    y += dpp_f64<kDppXor1>(y);
+    y += dpp_f64<kDppXor2>(y);
+    y += dpp_f64<kDppHalfMirror>(y);
+    if ((lane & 7) == 0) red.v[wid][lane >> 3] = y;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < 8) {
+        r = red.v[0][threadIdx.x];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) r += red.v[w][threadIdx.x];
+    }
+    __syncthreads();   // red is reused by the caller
+    return r;
 }
 
 // Fixed-order workgroup sum of NV partials; result valid in thread 0.

@@ -228,8 +228,8 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
         double part[8] = {rm * sr[0], rp * sr[1], rm * se[0], rp * se[1],
                           rp * mn[0][0] + rm * mn[0][1], rm * mx[0][0] + rp * mx[0][1],
                           rp * mn[1][0] + rm * mn[1][1], rm * mx[1][0] + rp * mx[1][1]};
-        block_sum<NT, 8>(part, red);
-        if (tid == 0) store_bounds<2>(p, e, part, flags);
+        const double sum = block_sum8<NT>(part, red);
+        if (tid < 8) store_bound_value<2>(p, e, tid, sum, flags);
     }
 }
 
