@@ -90,6 +90,56 @@ struct OpSum { __device__ static double f(double a, double b) { return a + b; } 
 struct OpMin { __device__ static double f(double a, double b) { return fmin(a, b); } };
 struct OpMax { __device__ static double f(double a, double b) { return fmax(a, b); } };
 
+// Lane swaps of gfx950 on doubles, one 32-bit half at a time.  ROW16 false
+// (v_permlane32_swap): lanes 32-63 of a <-> lanes 0-31 of b.  ROW16 true
+// (v_permlane16_swap): odd rows of a <-> even rows of b (rows of 16 lanes).
+template <bool ROW16>
+__device__ __forceinline__ void lane_swap(double& a, double& b) {
+    const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+    const unsigned alo = (unsigned)ia, ahi = (unsigned)(ia >> 32);
+    const unsigned blo = (unsigned)ib, bhi = (unsigned)(ib >> 32);
+    const auto lo = ROW16 ? __builtin_amdgcn_permlane16_swap(alo, blo, false, false)
+                          : __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto hi = ROW16 ? __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false)
+                          : __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
+    b = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
+}
+
+// Eight wave reductions at once, by transposition: each exchange stage
+// halves the number of values a lane carries, so a wave spends about 35 VALU
+// ops where eight separate reductions spend about 190.
+//  1. v[k] and v[k + 4] exchange half-waves: lanes 0-31 then carry values
+//     0-3 combined over lanes l and l + 32, lanes 32-63 values 4-7.
+//  2. v[0] and v[2], v[1] and v[3] exchange rows: row r of v[0] carries
+//     value 2r, of v[1] value 2r + 1.
+//  3. Within a row, lanes 0-7 keep v[0] and lanes 8-15 v[1] (exchange over
+//     lane bit 3), then bits 0-2 go over the DPP network.
+// Returns in lane l the reduction of value l / 8 over the wave (identical
+// across lanes l / 8 * 8 ... + 7).  The order of the combinations is fixed,
+// so sums are deterministic.  All 64 lanes must be active.
+template <class Op>
+__device__ __forceinline__ double wave_transpose8(double* v) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        lane_swap<false>(v[k], v[k + 4]);
+        v[k] = Op::f(v[k], v[k + 4]);
+    }
+    lane_swap<true>(v[0], v[2]);
+    v[0] = Op::f(v[0], v[2]);
+    lane_swap<true>(v[1], v[3]);
+    v[1] = Op::f(v[1], v[3]);
+    const bool upper = (lane & 8) != 0;
+    double y = upper ? v[1] : v[0];
+    const double give = upper ? v[0] : v[1];
+    y = Op::f(y, dpp_f64<kDppRor8>(give));
+    y = Op::f(y, dpp_f64<kDppXor1>(y));
+    y = Op::f(y, dpp_f64<kDppXor2>(y));
+    y = Op::f(y, dpp_f64<kDppHalfMirror>(y));
+    return y;
+}
+
 template <class Op>
 __device__ __forceinline__ double wave_reduce(double v) {
     v = Op::f(v, dpp_f64<kDppXor1>(v));
@@ -172,8 +222,9 @@ __device__ __forceinline__ double exp_tab(double x, const ExpPair* tab) {
     // clamps every accumulator of the caller at once (register pressure)
     asm volatile("" : "+v"(x));
     x = fmax(x, -1100.0);
-    const double n = rint(x * kInvStep);
-    const int ni = (int)n;
+    const double t = fma(x, kInvStep, 0x1.8p52);
+    const double n = t - 0x1.8p52;
+    const int ni = __double2loint(t);
     double r = fma(-n, kLn2By256Hi, x);
     r = fma(-n, kLn2By256Lo, r);
     double q = r + 4.0;
@@ -278,34 +329,31 @@ __device__ uint32_t stencil_prologue(const BoundsArgs& p, int64_t row0, int64_t 
         }
     }
     if (tid == 0) red.flags = 0;
-    lx = wave_min(lx); hx = wave_max(hx);
-    if (D >= 2) { ly = wave_min(ly); hy = wave_max(hy); }
-    if (D == 3) { lz = wave_min(lz); hz = wave_max(hz); }
-    if (ref) { ra = wave_max(ra); rl = wave_max(rl); }
+    // one transposed minimum over the wave for the box ends and log-peaks,
+    // maxima taken as minima of the negated values (exact)
+    double ext[8] = {lx, -hx, ly, -hy, lz, -hz, -ra, -rl};
+    const double m = wave_transpose8<OpMin>(ext);
     __syncthreads();
     if (bad) atomicOr(&red.flags, bad);
-    if (lane == 0) {
-        red.v[wid][0] = lx; red.v[wid][1] = hx; red.v[wid][2] = ly; red.v[wid][3] = hy;
-        red.v[wid][4] = lz; red.v[wid][5] = hz;
-        red.v[wid][6] = ra; red.v[wid][7] = rl;
-    }
+    if ((lane & 7) == 0) red.v[wid][lane >> 3] = m;
     __syncthreads();
-    if (ref) {
-        ref[0] = red.v[0][6];
-        ref[1] = red.v[0][7];
+    // wave w's extremum j sits in red.v[w][j]; the maxima are negated
+    auto ext_min = [&](int j) {
+        double r = red.v[0][j];
 #pragma unroll
-        for (int w = 1; w < NW; ++w) { ref[0] = fmax(ref[0], red.v[w][6]); ref[1] = fmax(ref[1], red.v[w][7]); }
+        for (int w = 1; w < NW; ++w) r = fmin(r, red.v[w][j]);
+        return r;
+    };
+    if (ref) {
+        ref[0] = -ext_min(6);
+        ref[1] = -ext_min(7);
     }
     if (p.grid_mode == KBL_GRID_STENCIL) {
 #pragma unroll
-        for (int j = 0; j < 2 * D; ++j) box[j] = red.v[0][j];
-#pragma unroll
-        for (int w = 1; w < NW; ++w)
-#pragma unroll
-            for (int j = 0; j < D; ++j) {
-                box[2 * j] = fmin(box[2 * j], red.v[w][2 * j]);
-                box[2 * j + 1] = fmax(box[2 * j + 1], red.v[w][2 * j + 1]);
-            }
+        for (int j = 0; j < D; ++j) {
+            box[2 * j] = ext_min(2 * j);
+            box[2 * j + 1] = -ext_min(2 * j + 1);
+        }
     } else {
         const double glo[3] = {p.lo0, p.lo1, p.lo2}, ghi[3] = {p.hi0, p.hi1, p.hi2};
 #pragma unroll
@@ -373,56 +421,15 @@ __device__ __forceinline__ void store_nan(const BoundsArgs& p, int64_t e, uint32
     if (p.status) p.status[e] = flags;
 }
 
-// Lane swaps of gfx950 on doubles, one 32-bit half at a time.  ROW16 false
-// (v_permlane32_swap): lanes 32-63 of a <-> lanes 0-31 of b.  ROW16 true
-// (v_permlane16_swap): odd rows of a <-> even rows of b (rows of 16 lanes).
-template <bool ROW16>
-__device__ __forceinline__ void lane_swap(double& a, double& b) {
-    const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
-    const unsigned alo = (unsigned)ia, ahi = (unsigned)(ia >> 32);
-    const unsigned blo = (unsigned)ib, bhi = (unsigned)(ib >> 32);
-    const auto lo = ROW16 ? __builtin_amdgcn_permlane16_swap(alo, blo, false, false)
-                          : __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
-    const auto hi = ROW16 ? __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false)
-                          : __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
-    a = __longlong_as_double(((long long)hi[0] << 32) | (long long)lo[0]);
-    b = __longlong_as_double(((long long)hi[1] << 32) | (long long)lo[1]);
-}
-
-// Fixed-order workgroup sum of 8 partials by transposition: each exchange
-// stage halves the number of values a lane carries, so a wave spends about
-// 40 VALU ops where eight separate wave sums spend about 200.
-//  1. v[k] and v[k + 4] exchange half-waves: lanes 0-31 then carry values
-//     0-3 summed over lanes l and l + 32, lanes 32-63 values 4-7.
-//  2. v[0] and v[2], v[1] and v[3] exchange rows: row r of v[0] carries
-//     value 2r, of v[1] value 2r + 1, each summed over 4 rows' worth.
-//  3. Within a row, lanes 0-7 keep v[0] and lanes 8-15 v[1] (exchange over
-//     lane bit 3), then bits 0-2 are summed on the DPP network: lane l then
-//     holds value l / 8 over the whole wave.
-//  4. Lanes 0, 8, ..., 56 publish their sums; thread t < 8 adds the waves'
-//     sums of value t in wave order.
-// All 64 lanes of every wave must be active.  Returns value t in thread
-// t < 8 (0 elsewhere).  Contains the barriers.
+// Fixed-order workgroup sum of 8 partials: wave_transpose8, then lanes 0,
+// 8, ..., 56 publish their wave's sums and thread t < 8 adds the waves' sums
+// of value t in wave order.  Returns value t in thread t < 8 (0 elsewhere).
+// All lanes active; contains the barriers.
 template <int NT>
 __device__ __forceinline__ double block_sum8(double* v, Red& red) {
     constexpr int NW = NT / 64;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        lane_swap<false>(v[k], v[k + 4]);
-        v[k] += v[k + 4];
-    }
-    lane_swap<true>(v[0], v[2]);
-    v[0] += v[2];
-    lane_swap<true>(v[1], v[3]);
-    v[1] += v[3];
-    const bool upper = (lane & 8) != 0;
-    double y = upper ? v[1] : v[0];
-    const double give = upper ? v[0] : v[1];
-    y += dpp_f64<kDppRor8>(give);
-    y += dpp_f64<kDppXor1>(y);
-    y += dpp_f64<kDppXor2>(y);
-    y += dpp_f64<kDppHalfMirror>(y);
+    const double y = wave_transpose8<OpSum>(v);
     if ((lane & 7) == 0) red.v[wid][lane >> 3] = y;
     __syncthreads();
     double r = 0.0;

@@ -114,7 +114,12 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
                     const double xj = node_pos(lox, j < p.nx ? j : p.nx - 1, hx);
                     __syncthreads();
                     if (sj < NT / NYM) {
-                        for (int s = sj; s < tn; s += NT / NYM) {
+                        // fully unrolled (LDS offsets become immediates)
+                        constexpr int kPass = NT / NYM;
+#pragma unroll
+                        for (int k = 0; k < (kTabStates + kPass - 1) / kPass; ++k) {
+                            const int s = sj + kPass * k;
+                            if (s >= tn) break;
                             const Coef c = sC[t0 + s];
                             const double d = yj - c.uy;
                             sB[s][j] = (c.nk * d) * d;
