@@ -497,27 +497,35 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d(BoundsArgs p) {
                 }
             }
         }
-        double part[6] = {0, 0, 0, 0, 0, 0};
+        // unrelaxed envelope sums, relaxed once per thread afterwards; the
+        // momentum sums split M u by sign (as in the 2D kernel)
+        double sr[2] = {0, 0}, se[2] = {0, 0}, mn[2] = {0, 0}, mx[2] = {0, 0};
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             const int j = tid + NT * i;
             if (j >= p.nx) continue;
             const double M = h * ((j == 0 || j == p.nx - 1) ? 0.5 : 1.0);
-                        const double ftn = rm * exp_tab(qtn[i], sExp);
-            const double ftx = rp * exp_tab(qtx[i], sExp);
-            const double fin = rm * exp_tab(qin[i], sExp);
-            const double fix = rp * exp_tab(qix[i], sExp);
+            const double gtn = exp_tab(qtn[i], sExp);
+            const double gtx = exp_tab(qtx[i], sExp);
+            const double gin = exp_tab(qin[i], sExp);
+            const double gix = exp_tab(qix[i], sExp);
             const double hu2 = 0.5 * u[i] * u[i];
-            part[0] += M * ftn;
-            part[1] += M * ftx;
-            part[2] += M * (hu2 * ftn + fin);
-            part[3] += M * (hu2 * ftx + fix);
-            if (u[i] < 0.0) { part[4] += M * u[i] * ftx; part[5] += M * u[i] * ftn; }
-            else            { part[4] += M * u[i] * ftn; part[5] += M * u[i] * ftx; }
+            sr[0] += M * gtn;
+            sr[1] += M * gtx;
+            se[0] += M * (hu2 * gtn + gin);
+            se[1] += M * (hu2 * gtx + gix);
+            const double mu = M * u[i];
+            const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+            mn[0] += neg * gtx;
+            mn[1] += pos * gtn;
+            mx[0] += neg * gtn;
+            mx[1] += pos * gtx;
             __builtin_amdgcn_sched_barrier(0);
         }
-        block_sum<NT, 6>(part, red);
-        if (tid == 0) store_bounds<1>(p, e, part, flags);
+        double part[8] = {rm * sr[0], rp * sr[1], rm * se[0], rp * se[1],
+                          rp * mn[0] + rm * mn[1], rm * mx[0] + rp * mx[1], 0.0, 0.0};
+        const double sum = block_sum8<NT>(part, red);
+        if (tid < 6) store_bound_value<1>(p, e, tid, sum, flags);
     }
 }
 
