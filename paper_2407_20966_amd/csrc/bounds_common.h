@@ -442,6 +442,36 @@ __device__ __forceinline__ double block_sum8(double* v, Red& red) {
     return r;
 }
 
+// Fixed-order workgroup sum of NV <= 16 partials by wave_transpose8 on
+// groups of eight (zero-padded); the sums are valid in thread 0 (part[0 ..
+// NV-1]).  All lanes active; contains the barriers.
+template <int NT, int NV>
+__device__ __forceinline__ void block_sum_t(double* part, Red& red) {
+    static_assert(NV >= 1 && NV <= 16, "up to 16 partials");
+    constexpr int NW = NT / 64;
+    constexpr int NG = (NV + 7) / 8;
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int g = 0; g < NG; ++g) {
+        double v[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v[k] = (8 * g + k < NV) ? part[8 * g + k] : 0.0;
+        const double y = wave_transpose8<OpSum>(v);
+        if ((lane & 7) == 0) red.v[wid][8 * g + (lane >> 3)] = y;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            double t = red.v[0][i];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) t += red.v[w][i];
+            part[i] = t;
+        }
+    }
+    __syncthreads();
+}
+
 // Fixed-order workgroup sum of NV partials; result valid in thread 0.
 template <int NT, int NV>
 __device__ __forceinline__ void block_sum(double* part, Red& red) {

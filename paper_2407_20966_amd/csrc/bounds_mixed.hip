@@ -362,7 +362,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                 }
             }
         }
-        block_sum<NT, kNP>(part, red);
+        block_sum_t<NT, kNP>(part, red);
         if (tid == 0) {
             const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
             const double eT = exp(ref[0]);
