@@ -334,14 +334,12 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
                     }
                 }
             lk = nlk;
-#pragma unroll
-            for (int k = 0; k < 5; ++k) z[k] = wave_sum(z[k]);
-            if (lane == 0)
-#pragma unroll
-                for (int k = 0; k < 5; ++k) sZw[wid][s][k] = z[k];
+            double zz[8] = {z[0], z[1], z[2], z[3], z[4], 0.0, 0.0, 0.0};
+            const double zs = wave_transpose8<OpSum>(zz);   // lane l: sum k = l / 8
+            if ((lane & 7) == 0 && (lane >> 3) < 5) sZw[wid][s][lane >> 3] = zs;
         }
         double ext[4] = {gl[0], gh[0], gl[1], gh[1]};
-        block_sum<NT, 4>(ext, red);      // valid in thread 0; contains the barriers
+        block_sum_t<NT, 4>(ext, red);    // valid in thread 0; contains the barriers
         if (tid == 0)
 #pragma unroll
             for (int k = 0; k < 4; ++k) red.v[0][8 + k] = ext[k];

@@ -372,7 +372,7 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
                 else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
             }
         }
-        block_sum<NT, 8>(part, red);
+        block_sum_t<NT, 8>(part, red);
         if (tid == 0) store_bounds<2>(p, e, part, flags);
     }
 }
@@ -440,7 +440,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
             if (u[i] < 0.0) { part[4] += M * u[i] * ftx; part[5] += M * u[i] * ftn; }
             else            { part[4] += M * u[i] * ftn; part[5] += M * u[i] * ftx; }
         }
-        block_sum<NT, 6>(part, red);
+        block_sum_t<NT, 6>(part, red);
         if (tid == 0) store_bounds<1>(p, e, part, flags);
     }
 }

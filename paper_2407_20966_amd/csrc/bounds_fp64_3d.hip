@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
                     }
                 }
             }
-            block_sum<NT, 10>(part, red);
+            block_sum_t<NT, 10>(part, red);
             if (tid == 0) {
 #pragma unroll
                 for (int v = 0; v < 10; ++v) sTot[v] = (z0 == 0 ? 0.0 : sTot[v]) + part[v];
