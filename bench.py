@@ -76,12 +76,16 @@ def kernel_sources_sha(dim: int) -> str:
 
 def profiled_traffic(kernel: str, grid_threads: int, workload: str, dim: int):
     """HBM bytes per launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE, scaled by the copy-kernel calibration), or None when there is
-    no entry for this kernel, launch shape and workload, or the kernel's
-    sources changed since the counters were taken (per-entry sha256)."""
+    WRITE_SIZE, scaled by the copy-kernel calibration) and the grid size the
+    counters were taken at, or (None, None) when there is no entry for this
+    kernel and workload, or the kernel's sources changed since the counters
+    were taken (per-entry sha256).  An entry at this launch's grid size is
+    preferred; else one of the same kernel at another grid size (the autotuner
+    may pick a persistent grid: the same element work, so the same bytes up to
+    L2 reuse)."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path) or dim not in KERNEL_SOURCES:
-        return None
+        return None, None
     entries, cur = [], None
     for line in open(path):
         line = line.strip()
@@ -95,14 +99,18 @@ def profiled_traffic(kernel: str, grid_threads: int, workload: str, dim: int):
             k, v = line.split("=", 1)
             cur[k.strip()] = v.strip()
     sha = kernel_sources_sha(dim)
+    other = (None, None)
     for e in entries:
         try:
-            if (e["kernel"] == kernel and int(e["grid_threads"]) == grid_threads
-                    and e["workload"] == workload and e["source_sha256"] == sha):
-                return float(e["bytes_per_launch"])
+            if e["kernel"] == kernel and e["workload"] == workload and e["source_sha256"] == sha:
+                g = int(e["grid_threads"])
+                if g == grid_threads:
+                    return float(e["bytes_per_launch"]), g
+                if other[0] is None:
+                    other = (float(e["bytes_per_launch"]), g)
         except (KeyError, ValueError):
             continue
-    return None
+    return other
 
 
 def pair_ops(dim: int) -> int:
@@ -330,13 +338,15 @@ def time_3d(args, kbl, torch, synth, stream):
     ops = wl.pairs() * pair_ops(3)
     print(f"[bench] hex32: {ms:.3f} ms/step (bounds {b_ms:.3f} ms, limit {l_ms:.3f} ms)",
           file=sys.stderr, flush=True)
-    traffic = profiled_traffic(kname, gthreads, "hex32", 3) if gthreads else None
+    traffic, traffic_grid = (profiled_traffic(kname, gthreads, "hex32", 3) if gthreads
+                             else (None, None))
     out = {"workload": f"hex32: {WORKLOAD_TEXT['hex32']}", "n_elem": wl.n_elem,
            "value": wl.n_elem / (ms * 1e-3), "unit": "elements/s", "ms_per_step": ms,
            "bounds_ms": b_ms, "limit_ms": l_ms, "kernel": kname, "grid_threads": gthreads,
            "pairs_per_launch": wl.pairs(), "ops_per_pair": pair_ops(3),
            "frac": ops / (b_ms * 1e-3) / VALU_PEAK_OPS, "traffic": traffic,
-           "traffic_unit": "bytes per launch", "launch": tuned, "parity_tol": 1e-12}
+           "traffic_unit": "bytes per launch", "traffic_grid_threads": traffic_grid, "launch": tuned,
+           "parity_tol": 1e-12}
     del st, tg, lim
     return out
 
@@ -473,11 +483,12 @@ def main(argv=None):
     achieved = ops / (b_ms * 1e-3)
     n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     kname, grid_threads = kernel_shape(kbl, wl.dim, tuned.get("fp64"), wl.n_elem, n_cu)
-    traffic = (profiled_traffic(kname, grid_threads, args.workload, wl.dim)
-               if grid_threads else None)
+    traffic, traffic_grid = (profiled_traffic(kname, grid_threads, args.workload, wl.dim)
+                             if grid_threads else (None, None))
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
             "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
             "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_FILE,
+            "traffic_grid_threads": traffic_grid,
             "kernel": kname, "grid_threads": grid_threads,
             "ops_per_launch": ops, "pairs_per_launch": pairs,
             "ops_per_pair": pair_ops(wl.dim), "kernel_ms": b_ms, "limit_ms": l_ms,

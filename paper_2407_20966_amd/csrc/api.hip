@@ -309,6 +309,11 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
                          : dim == 2 ? (prec == KBL_PREC_FP64 ? kbl::bounds_default_tile_2d(a.nx, a.ny)
                                                              : kbl::mixed_default_tile_2d(a.nx, a.ny, prec))
                                     : -1;
+    // bring the clocks up first: the first launches after idle run slower, and
+    // the default, timed first, would otherwise be measured at lower clocks
+    s.grid_blocks = 0;
+    for (int r = 0; r < 10; ++r)
+        if (launch_bounds_any(s, dim, prec, def_tile, st) != hipSuccess) break;
     float best = 1e30f;
     TuneVal bestv{-1, 0};
     int best_idx = -1;
