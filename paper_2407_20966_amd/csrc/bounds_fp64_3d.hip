@@ -26,8 +26,13 @@
 namespace kbl {
 namespace {
 
+// Two waves per SIMD are required of the register allocation (256 VGPRs): the
+// 3 x 3 x 2 tile needs a few more in the contraction, and the compiler then
+// keeps some element-invariant values in scratch (reloaded once per node)
+// instead of halving the occupancy.
 template <int BX, int BY, int BZ, int TX, int TY, int TZ>
-__global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
+__global__ __launch_bounds__(BX * BY * BZ) __attribute__((amdgpu_waves_per_eu(2)))
+void bounds_fp64_3d(BoundsArgs p) {
     constexpr int NT = BX * BY * BZ;
     constexpr int NXM = BX * TX;   // x nodes covered
     constexpr int NYM = BY * TY;   // y nodes covered
@@ -40,11 +45,13 @@ __global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
     __shared__ double sZ[kTab][NZP];
     __shared__ double sL[kTab];
     __shared__ double sTot[10];    // moment sums of the finished slabs (thread 0)
+    __shared__ ExpPair sExp[256];
     __shared__ Red red;
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = (tid / BX) % BY, tz = tid / (BX * BY);
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
     for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
@@ -179,10 +186,10 @@ __global__ __launch_bounds__(BX * BY * BZ) void bounds_fp64_3d(BoundsArgs p) {
                         const int jz = z0 + otz + BZ * k;
                         if (jz >= p.nz) continue;
                         const double M = wxy * (dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0));
-                        const double ftn = rm * exp(qtn[i][j][k]);
-                        const double ftx = rp * exp(qtx[i][j][k]);
-                        const double fin = rm * exp(qin[i][j][k]);
-                        const double fix = rp * exp(qix[i][j][k]);
+                        const double ftn = rm * exp_tab(qtn[i][j][k], sExp);
+                        const double ftx = rp * exp_tab(qtx[i][j][k], sExp);
+                        const double fin = rm * exp_tab(qin[i][j][k], sExp);
+                        const double fix = rp * exp_tab(qix[i][j][k], sExp);
                         const double hu2 = 0.5 * ux[i] * ux[i] + 0.5 * uy[j] * uy[j] + 0.5 * uz[k] * uz[k];
                         part[0] += M * ftn;
                         part[1] += M * ftx;
