@@ -178,14 +178,24 @@ struct ElemRange {
     int64_t e, end, step;
 };
 __device__ __forceinline__ ElemRange xcd_range(int64_t n) {
+    static_assert(kXcds == 8, "shifts below assume 8 XCDs");
     const int64_t G = gridDim.x, b = blockIdx.x;
-    const int64_t nx = G < kXcds ? G : kXcds;             // XCD groups that own workgroups
-    const int64_t x = b % nx, j = b / nx;
-    const int64_t gx = G / nx + (x < G % nx ? 1 : 0);     // workgroups in group x
-    const int64_t q = n / nx, r = n % nx;
-    const int64_t start = x * q + (x < r ? x : r);
-    const int64_t cnt = q + (x < r ? 1 : 0);
-    return ElemRange{start + j, start + cnt, gx};
+    if (G >= kXcds) {
+        // the usual case, in shifts and masks: all scalar work (a 64-bit
+        // division of uniform values would be expanded on the VALU, about a
+        // hundred instructions per workgroup)
+        const int64_t x = b & (kXcds - 1), j = b >> 3;
+        const int64_t gx = (G >> 3) + (x < (G & (kXcds - 1)) ? 1 : 0);
+        const int64_t q = n >> 3, r = n & (kXcds - 1);
+        const int64_t start = x * q + (x < r ? x : r);
+        const int64_t cnt = q + (x < r ? 1 : 0);
+        return ElemRange{start + j, start + cnt, gx};
+    }
+    // fewer workgroups than XCDs: one group per workgroup
+    const int64_t q = n / G, r = n % G;
+    const int64_t start = b * q + (b < r ? b : r);
+    const int64_t cnt = q + (b < r ? 1 : 0);
+    return ElemRange{start, start + cnt, 1};
 }
 
 // Ends of one state's velocity interval U -+ k sqrt(theta) (eq. truncdomain).
