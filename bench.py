@@ -57,9 +57,10 @@ WORKLOAD_TEXT = {
 # sources of the FP64 bounds kernels, per velocity dimension
 KERNEL_SOURCES = {
     2: ("paper_2407_20966_amd/csrc/bounds_fp64.hip", "paper_2407_20966_amd/csrc/bounds_common.h",
-        "paper_2407_20966_amd/csrc/kbl_internal.h"),
+        "paper_2407_20966_amd/csrc/kbl_internal.h", "paper_2407_20966_amd/csrc/exp2_table.h"),
     3: ("paper_2407_20966_amd/csrc/bounds_fp64_3d.hip",
-        "paper_2407_20966_amd/csrc/bounds_common.h", "paper_2407_20966_amd/csrc/kbl_internal.h"),
+        "paper_2407_20966_amd/csrc/bounds_common.h", "paper_2407_20966_amd/csrc/kbl_internal.h",
+        "paper_2407_20966_amd/csrc/exp2_table.h"),
 }
 TRAFFIC_FILE = "profiles/bounds_fp64_traffic.txt"
 
