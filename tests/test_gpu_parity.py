@@ -192,6 +192,27 @@ def test_monatomic_gamma(kbl):
     check_workload(kbl, wl1)
 
 
+@pytest.mark.parametrize("case", ["quad", "line"])
+def test_extreme_temperature_ratio(kbl, case):
+    """Every fifth element at rest with theta = 1e-12 among states at theta
+    of order 1: far out in the cold states' tails the log-Maxwellian reaches
+    about -1e13 (per-stencil box, quad) or -7e13 (global box, line), beyond
+    the 32-bit range of the exp's argument reduction, which clamps first; the
+    envelopes underflow to 0 and rho_min is floored, as in the oracle."""
+    if case == "quad":
+        wl = synth.make_quad_workload(N=8, seed=71, grid_nodes=32, name="quad_cold")
+    else:
+        wl = synth.make_line_workload(n_elem=64, seed=72, name="line_cold")
+    d = wl.dim
+    st = wl.states.copy()
+    cold = np.arange(wl.n_elem)[::5]
+    nodes = (cold[:, None] * wl.n_s + np.arange(wl.n_s)[None, :]).ravel()
+    st[1:1 + d, nodes] = 0.0
+    st[d + 1, nodes] = 1e-12 * st[0, nodes] / (wl.gamma - 1.0)
+    wl.states = st
+    check_workload(kbl, wl)
+
+
 def test_single_element_stencils(kbl):
     wl = synth.make_quad_workload(N=6, seed=12, grid_nodes=40, name="quad_self")
     wl.rowptr = np.arange(wl.n_elem + 1, dtype=np.int32)
