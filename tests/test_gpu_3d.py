@@ -130,6 +130,20 @@ def test_hex_gamma(kbl, gamma):
     check(kbl, hex_wl(2, (20, 20, 20), seed=13, gamma=gamma, name=f"hex_g{gamma:.3f}"))
 
 
+def test_hex_extreme_temperature_ratio(kbl):
+    """Every fifth element at rest with theta = 1e-12: the log-Maxwellian
+    reaches about -1e13 in the cold states' tails (clamped exp, underflow
+    to 0, rho_min floored), as in the oracle."""
+    wl = hex_wl(2, (12, 12, 12), seed=16, name="hex_cold")
+    st = wl.states.copy()
+    cold = np.arange(wl.n_elem)[::5]
+    nodes = (cold[:, None] * wl.n_s + np.arange(wl.n_s)[None, :]).ravel()
+    st[1:4, nodes] = 0.0
+    st[4, nodes] = 1e-12 * st[0, nodes] / (wl.gamma - 1.0)
+    wl.states = st
+    check(kbl, wl)
+
+
 def test_hex_strict_bounds_and_independent_alpha(kbl):
     wl = hex_wl(3, (12, 12, 12), seed=14, name="hex_r0")
     check(kbl, wl, r_fac=0.0)
