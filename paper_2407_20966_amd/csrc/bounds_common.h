@@ -59,13 +59,12 @@ __device__ __forceinline__ Prim load_prim(const BoundsArgs& p, int64_t node) {
     return s;
 }
 
-// Wave64 reductions on the DPP lane network (no LDS round trips).  Inside
-// each row of 16 lanes: swap neighbours, swap pairs (quad_perm), then the
-// half-row and row mirrors; every lane of a row then holds the row result,
-// bit-identical across the row because each step combines the same two
-// operands.  The four row results are read out with readlane and combined
-// in a fixed order, so the wave result is deterministic and uniform.  All 64
-// lanes must be active.
+// Wave64 reductions on the lane networks (no LDS round trips): DPP inside
+// rows of 16 lanes (neighbour and pair swaps by quad_perm, half-row and row
+// mirrors, row rotation by 8) and gfx950's permlane swaps across rows and
+// half-waves.  Each step combines the same two operands in every lane that
+// keeps the result, so results are bit-identical across those lanes and
+// deterministic.  All 64 lanes must be active.
 constexpr int kDppXor1 = 0xB1;          // quad_perm [1,0,3,2]
 constexpr int kDppXor2 = 0x4E;          // quad_perm [2,3,0,1]
 constexpr int kDppHalfMirror = 0x141;   // row_half_mirror
@@ -79,16 +78,9 @@ __device__ __forceinline__ double dpp_f64(double v) {
     const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
-__device__ __forceinline__ double lane_f64(double v, int lane) {
-    const long long b = __double_as_longlong(v);
-    const int lo = __builtin_amdgcn_readlane((int)b, lane);
-    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
-    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
-}
 
 struct OpSum { __device__ static double f(double a, double b) { return a + b; } };
 struct OpMin { __device__ static double f(double a, double b) { return fmin(a, b); } };
-struct OpMax { __device__ static double f(double a, double b) { return fmax(a, b); } };
 
 // Lane swaps of gfx950 on doubles, one 32-bit half at a time.  ROW16 false
 // (v_permlane32_swap): lanes 32-63 of a <-> lanes 0-31 of b.  ROW16 true
@@ -140,18 +132,8 @@ __device__ __forceinline__ double wave_transpose8(double* v) {
     return y;
 }
 
-template <class Op>
-__device__ __forceinline__ double wave_reduce(double v) {
-    v = Op::f(v, dpp_f64<kDppXor1>(v));
-    v = Op::f(v, dpp_f64<kDppXor2>(v));
-    v = Op::f(v, dpp_f64<kDppHalfMirror>(v));
-    v = Op::f(v, dpp_f64<kDppMirror>(v));
-    return Op::f(Op::f(lane_f64(v, 0), lane_f64(v, 16)), Op::f(lane_f64(v, 32), lane_f64(v, 48)));
-}
-__device__ __forceinline__ double wave_sum(double v) { return wave_reduce<OpSum>(v); }
-__device__ __forceinline__ double wave_min(double v) { return wave_reduce<OpMin>(v); }
-__device__ __forceinline__ double wave_max(double v) { return wave_reduce<OpMax>(v); }
-
+// Integer minimum over the wave, uniform: rows on DPP, then the four row
+// results by readlane in a fixed order.
 __device__ __forceinline__ int wave_min_i32(int v) {
     v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor1, 0xF, 0xF, false));
     v = min(v, __builtin_amdgcn_update_dpp(0, v, kDppXor2, 0xF, 0xF, false));
@@ -482,31 +464,6 @@ __device__ __forceinline__ void block_sum_t(double* part, Red& red) {
     __syncthreads();
 }
 
-// Fixed-order workgroup sum of NV partials; result valid in thread 0.
-template <int NT, int NV>
-__device__ __forceinline__ void block_sum(double* part, Red& red) {
-    constexpr int NW = NT / 64;
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) part[i] = wave_sum(part[i]);
-    if (NW > 1) {
-        if (lane == 0) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) red.v[wid][i] = part[i];
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int i = 0; i < NV; ++i) {
-                double s = red.v[0][i];
-#pragma unroll
-                for (int w = 1; w < NW; ++w) s += red.v[w][i];
-                part[i] = s;
-            }
-        }
-        __syncthreads();
-    }
-}
 
 }  // namespace
 }  // namespace kbl
