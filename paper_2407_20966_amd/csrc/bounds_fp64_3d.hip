@@ -39,6 +39,7 @@ void bounds_fp64_3d(BoundsArgs p) {
     constexpr int NZP = BZ * TZ;   // z nodes per slab
     constexpr int kTab = 32;       // states per table chunk
     static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
+    static_assert(NXM == NYM && NXM <= NT && NZP <= NT, "A and B tables built together");
     __shared__ Coef3 sC[kMaxStates];
     __shared__ double sA[kTab][NXM];
     __shared__ double sB[kTab][NYM];
@@ -98,26 +99,36 @@ void bounds_fp64_3d(BoundsArgs p) {
                     asm volatile("" : "+v"(bx0), "+v"(by0), "+v"(bz0), "+v"(bhx), "+v"(bhy),
                                  "+v"(bhz), "+v"(otid));
                     __syncthreads();
-                    for (int idx = otid; idx < tn * NXM; idx += NT) {
-                        const int s = idx / NXM, i = idx - s * NXM;
-                        const int ic = i < p.nx ? i : p.nx - 1;
-                        const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(bx0, ic, bhx) - c.ux;
-                        sA[s][i] = fma(c.nk * d, d, c.a);
-                    }
-                    for (int idx = otid; idx < tn * NYM; idx += NT) {
-                        const int s = idx / NYM, j = idx - s * NYM;
-                        const int jc = j < p.ny ? j : p.ny - 1;
-                        const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(by0, jc, bhy) - c.uy;
-                        sB[s][j] = (c.nk * d) * d;
-                    }
-                    for (int idx = otid; idx < tn * NZP; idx += NT) {
-                        const int s = idx / NZP, k = idx - s * NZP;
-                        const int jz = z0 + k < p.nz ? z0 + k : p.nz - 1;
-                        const Coef3& c = sC[t0 + s];
-                        const double d = node_pos(bz0, jz, bhz) - c.uz;
-                        sZ[s][k] = (c.nk * d) * d;
+                    // A and B by columns: thread t fills node t % NXM of
+                    // states t / NXM, t / NXM + NT / NXM, ... (one node
+                    // coordinate per thread, no index division per entry);
+                    // C likewise over the slab's NZP planes
+                    {
+                        constexpr int kPass = NT / NXM;
+                        const int ja = otid % NXM, sa = otid / NXM;
+                        const double xa = node_pos(bx0, ja < p.nx ? ja : p.nx - 1, bhx);
+                        const double ya = node_pos(by0, ja < p.ny ? ja : p.ny - 1, bhy);
+                        if (sa < kPass) {
+#pragma unroll
+                            for (int k = 0; k < (kTab + kPass - 1) / kPass; ++k) {
+                                const int s = sa + kPass * k;
+                                if (s >= tn) break;
+                                const Coef3& c = sC[t0 + s];
+                                const double dx = xa - c.ux;
+                                sA[s][ja] = fma(c.nk * dx, dx, c.a);
+                                const double dy = ya - c.uy;
+                                sB[s][ja] = (c.nk * dy) * dy;
+                            }
+                        }
+                        constexpr int kPassZ = NT / NZP;
+                        const int kz = otid % NZP, sz = otid / NZP;
+                        const int jz = z0 + kz < p.nz ? z0 + kz : p.nz - 1;
+                        const double za = node_pos(bz0, jz, bhz);
+                        for (int s = sz; s < tn; s += kPassZ) {
+                            const Coef3& c = sC[t0 + s];
+                            const double dz = za - c.uz;
+                            sZ[s][kz] = (c.nk * dz) * dz;
+                        }
                     }
                     for (int s = otid; s < tn; s += NT) sL[s] = sC[t0 + s].al - sC[t0 + s].a;
                     __syncthreads();
