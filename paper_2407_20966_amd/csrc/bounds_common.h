@@ -198,15 +198,16 @@ __device__ __forceinline__ double box_hi(double u, double k, double sd) {
 }
 // exp for the moment contraction, by Tang's table-driven method (ACM TOMS
 // 15(2), 1989): x = (256 m + j) ln(2)/256 + r with |r| <= ln(2)/512, so that
-// exp(x) = 2^m 2^(j/256) exp(r).  exp(r) - 1 is its degree-4 Taylor
-// polynomial (remainder below 4e-17), evaluated as
-// r (24 + r (12 + r (4 + r))) / 24 with the 1/24 taken from the table
-// (T/24 next to T): every constant then fits the one scalar operand an
-// instruction may read.  r is reduced with ln(2)/256 in two parts.  Error
-// about 1 ulp.  The argument is clamped below at -1100 (-inf gives 0); the
-// callers' arguments are bounded above by the log-peaks of admissible states.
-// 14 VALU ops and one LDS read, against 22 VALU ops of the general-purpose
-// exp.  tab: the table staged in LDS by stage_exp_table (a global table read
+// exp(x) = 2^m 2^(j/256) exp(r).  n = 256 m + j is rounded by adding
+// 1.5 2^52, which leaves n in the low word of the sum; r is reduced with
+// ln(2)/256 in two parts.  exp(r) - 1 is its degree-4 Taylor polynomial
+// (remainder below 4e-17), evaluated as r (24 + r (12 + r (4 + r))) / 24 with
+// the 1/24 taken from the table (T/24 next to T), so that the polynomial's
+// constants are inline or one scalar operand each.  Error about 1 ulp.  The
+// argument is clamped below at -1100 (-inf gives 0); the callers' arguments
+// are bounded above by the log-peaks of admissible states (far below the
+// 5.8e6 at which n would leave 32 bits).  14 VALU ops and one LDS read,
+// against 22 VALU ops of the general-purpose exp.  tab: the table staged in LDS by stage_exp_table (a global table read
 // per lane waits on memory latency).
 __device__ __forceinline__ double exp_tab(double x, const ExpPair* tab) {
     constexpr double kInvStep = 0x1.71547652b82fep+8;   // 256 / ln 2
