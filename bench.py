@@ -372,13 +372,26 @@ def time_fr1d(args, kbl, torch, stream):
         s.step(0.1 * h / ((2 * pr.p + 1) * sp))
     torch.cuda.synchronize()
     ms_cfl = 1e3 * (time.perf_counter() - t0) / steps
+    # the CFL time step computed on the device, steps replayed from a HIP graph
+    # in batches of 50 (no host sync per step; the capture is included)
+    g = kbl.FR1D(pr.p, pr.n_elem, pr.x0, pr.x1, pr.gamma, bc=pr.bc, left=pr.left,
+                 right=pr.right, r_fac=1e-3, n_u=2048, k=8.0, stream=stream)
+    g.set_solution(pr.U0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    n_graph = g.run_device(10 * steps * dt, 0.1, batch=50)
+    torch.cuda.synchronize()
+    ms_graph = 1e3 * (time.perf_counter() - t0) / max(n_graph, 1)
+    del g
     pairs = 3 * (pr.n_elem * (pr.p + 5) + 2 * (pr.p + 3)) * 2048
-    print(f"[bench] fr1d sod p=3 N=3200: {ms:.3f} ms/step ({ms_cfl:.3f} with the CFL sync)",
+    print(f"[bench] fr1d sod p=3 N=3200: {ms:.3f} ms/step ({ms_cfl:.3f} with the CFL sync, "
+          f"{ms_graph:.3f} with the device CFL step in HIP graphs over {n_graph} steps)",
           file=sys.stderr, flush=True)
     return {"workload": "Sod shock tube, FR p=3, 3200 elements, HLLC, SSP-RK3 with the kinetic "
                         "bounds (k=8, 2048 velocity nodes, node stencils of 10 states) and the "
                         "squeeze limiter after every stage",
             "ms_per_step": ms, "steps_per_s": 1e3 / ms, "ms_per_step_with_cfl_sync": ms_cfl,
+            "ms_per_step_device_cfl_graph": ms_graph, "graph_steps": n_graph,
             "element_stages_per_s": 3 * pr.n_elem / (ms * 1e-3),
             "bounds_pairs_per_step": pairs,
             "launches_per_step": 14}
