@@ -258,11 +258,14 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
     __shared__ double sEA[kTabStates][NXM];
     __shared__ double sEB[kTabStates][NYM];
     __shared__ double sCs[kTabStates];        // theta delta / 2 per state
+    __shared__ ExpPair sExp[256];
     __shared__ Red red;
+    static_assert(NXM == NYM && NXM <= NT, "tables built by columns");
 
     const int tid = threadIdx.x;
     const int tx = tid % BX, ty = tid / BX;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
     for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
@@ -308,19 +311,22 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
             for (int t0 = 0; t0 < cn; t0 += kTabStates) {
                 const int tn = (cn - t0) < kTabStates ? (cn - t0) : kTabStates;
                 __syncthreads();
-                for (int idx = tid; idx < tn * NXM; idx += NT) {
-                    const int s = idx / NXM, i = idx - s * NXM;
-                    const int ic = i < p.nx ? i : p.nx - 1;
-                    const Coef& c = sC[t0 + s];
-                    const double d = node_pos(lox, ic, hx) - c.ux;
-                    sEA[s][i] = exp(fma(c.nk * d, d, c.a));
-                }
-                for (int idx = tid; idx < tn * NYM; idx += NT) {
-                    const int s = idx / NYM, j = idx - s * NYM;
-                    const int jc = j < p.ny ? j : p.ny - 1;
-                    const Coef& c = sC[t0 + s];
-                    const double d = node_pos(loy, jc, hy) - c.uy;
-                    sEB[s][j] = exp((c.nk * d) * d);
+                {
+                    // by columns: thread t fills node t % NXM of states
+                    // t / NXM, t / NXM + NT / NXM, ...
+                    constexpr int kPass = NT / NXM;
+                    const int j = tid % NXM, sj = tid / NXM;
+                    const double xj = node_pos(lox, j < p.nx ? j : p.nx - 1, hx);
+                    const double yj = node_pos(loy, j < p.ny ? j : p.ny - 1, hy);
+                    if (sj < kPass) {
+                        for (int s = sj; s < tn; s += kPass) {
+                            const Coef& c = sC[t0 + s];
+                            const double dx = xj - c.ux;
+                            sEA[s][j] = exp_tab(fma(c.nk * dx, dx, c.a), sExp);
+                            const double dy = yj - c.uy;
+                            sEB[s][j] = exp_tab((c.nk * dy) * dy, sExp);
+                        }
+                    }
                 }
                 for (int s = tid; s < tn; s += NT) sCs[s] = p.half_delta * (-0.5 / sC[t0 + s].nk);
                 __syncthreads();
@@ -381,9 +387,11 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
 template <int NT, int T>
 __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
     __shared__ Coef sC[kMaxStates];
+    __shared__ ExpPair sExp[256];
     __shared__ Red red;
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
+    stage_exp_table<NT>(sExp);   // published by the prologue's barriers
     for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
@@ -417,7 +425,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
                     const double d = u[i] - c.ux;
-                    const double g = exp(fma(c.nk * d, d, c.a));
+                    const double g = exp_tab(fma(c.nk * d, d, c.a), sExp);
                     const double eg = g * (hu[i] + cs);
                     gn[i] = fmin(gn[i], g);
                     gx[i] = fmax(gx[i], g);
