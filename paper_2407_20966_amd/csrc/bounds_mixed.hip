@@ -197,11 +197,20 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
         for (int c0 = 0; c0 < ns; c0 += kTab) {
             const int cn = (ns - c0) < kTab ? (ns - c0) : kTab;
             __syncthreads();
-            for (int idx = tid; idx < cn * NY; idx += NT) {
-                const int s = idx / NY, j = idx - s * NY;
-                const float uyc = (float)(node_pos(box[2], j < p.ny ? j : p.ny - 1, hy) - cy);
-                const float d = uyc - sF[c0 + s].uy;
-                stage.b[s][j] = (sF[c0 + s].nk * d) * d;
+            {
+                // by columns: thread t fills node t % NY of states t / NY,
+                // t / NY + NT / NY, ... (one node coordinate per thread, no
+                // index division per entry); the same values as per entry
+                static_assert(NY <= NT, "one column per thread at least");
+                constexpr int kPass = NT / NY;
+                const int j = tid % NY, sj = tid / NY;
+                if (sj < kPass) {
+                    const float uyc = (float)(node_pos(box[2], j < p.ny ? j : p.ny - 1, hy) - cy);
+                    for (int s = sj; s < cn; s += kPass) {
+                        const float d = uyc - sF[c0 + s].uy;
+                        stage.b[s][j] = (sF[c0 + s].nk * d) * d;
+                    }
+                }
             }
             __syncthreads();
             int s = 0;
