@@ -184,3 +184,22 @@ def test_energy_perstate_monatomic(kbl):
     # delta = 0: the per-state integrand is g |u|^2 / 2, as in the default reading
     wl = synth.make_quad_workload(N=6, seed=93, grid_nodes=32, gamma=2.0, name="eA_mono")
     check_energy(kbl, wl)
+
+
+@pytest.mark.parametrize("case", ["quad", "line"])
+def test_energy_perstate_extreme_temperature_ratio(kbl, case):
+    """Every fifth element at rest with theta = 1e-12 among states at theta
+    ~ 1: the value-space factors exp(A), exp(B) of the cold states underflow
+    to 0 over most of the box (clamped table exp), as in the oracle."""
+    if case == "quad":
+        wl = synth.make_quad_workload(N=8, seed=94, grid_nodes=32, name="eA_cold")
+    else:
+        wl = synth.make_line_workload(n_elem=64, seed=95, name="eA_cold_line")
+    d = wl.dim
+    st = wl.states.copy()
+    cold = np.arange(wl.n_elem)[::5]
+    nodes = (cold[:, None] * wl.n_s + np.arange(wl.n_s)[None, :]).ravel()
+    st[1:1 + d, nodes] = 0.0
+    st[d + 1, nodes] = 1e-12 * st[0, nodes] / (wl.gamma - 1.0)
+    wl.states = st
+    check_energy(kbl, wl)
