@@ -7,9 +7,11 @@
 //    relaxation factors of eq. relaxed, the final scaling and the density
 //    floor of Sec. 3.8.
 //  - FP32: the envelopes.  Coefficients are shifted by the element's log-peak
-//    reference (so exp lands in (0, 1]) and velocities are centred on the
-//    box, then q = A[x] + B[y] and the four running extrema are kept in FP32;
-//    two states are folded per step with three-input min/max.
+//    reference and velocities are centred on the box, then q = A[x] + B[y]
+//    and the four running extrema are kept in FP32; two states are folded
+//    per step with three-input min/max.  On the MFMA paths each envelope is
+//    then exponentiated relative to a power of two at its maximum over the
+//    wave's nodes.
 //  - Contraction of the moments (eq. rhobounds, Ebounds, mmbounds, mpbounds)
 //    with the trapezoid weights (Sec. 3.7).  The weights and moment
 //    polynomials are separable, M psi(u) = X(ux) Y(uy), so the contraction
@@ -53,6 +55,23 @@ __device__ __forceinline__ short f2bf(float x) {   // round to nearest even
 }
 __device__ __forceinline__ float bf2f(short b) {
     return __uint_as_float(((uint32_t)(uint16_t)b) << 16);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f32(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// Maximum over the wave, uniform: rows on DPP, then the four row results by
+// readlane.
+__device__ __forceinline__ float wave_max_f32(float v) {
+    v = fmaxf(v, dpp_f32<kDppXor1>(v));
+    v = fmaxf(v, dpp_f32<kDppXor2>(v));
+    v = fmaxf(v, dpp_f32<kDppHalfMirror>(v));
+    v = fmaxf(v, dpp_f32<kDppMirror>(v));
+    const int b = __float_as_int(v);
+    return fmaxf(fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 0)), __int_as_float(__builtin_amdgcn_readlane(b, 16))),
+                 fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)), __int_as_float(__builtin_amdgcn_readlane(b, 48))));
 }
 
 // y-stage contraction of one envelope (one x tile) on MFMA: returns C
@@ -264,6 +283,37 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             }
         }
 
+        // MFMA paths: each envelope is exponentiated relative to its largest
+        // value over the wave's nodes, rounded up to a power of two:
+        // f = 2^(q log2 e - n) with n = ceil(max q log2 e), so the wave's
+        // largest value lies in (1/2, 1] however far the stencil's log-peaks
+        // spread.  The FP16/BF16 splits of the y stage resolve values down to
+        // ~2^-38 of the largest; without the shift, states at theta ~ 1
+        // beside a nearly cold one (~1e-12 below the cold log-peak) would be
+        // lost.  The wave's FP64 partials are scaled back by 2^n exactly
+        // before the workgroup sum.  An envelope that is -inf everywhere (no
+        // internal energy term) keeps n = 0 and exponentiates to 0; n is
+        // clamped at -2000, where both sides of the scaling underflow to 0.
+        // The FP32 VALU path needs no shift: its exp reaches e^-87.
+        float nsh[4] = {0.f, 0.f, 0.f, 0.f};   // n, uniform over the wave
+        if (CT != KBL_PREC_MIXED_FP32) {
+            float em[4] = {-kInfF, -kInfF, -kInfF, -kInfF};
+#pragma unroll
+            for (int i = 0; i < TXW; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    em[0] = fmaxf(em[0], tn[i][j]);
+                    em[1] = fmaxf(em[1], tX[i][j]);
+                    em[2] = fmaxf(em[2], in_[i][j]);
+                    em[3] = fmaxf(em[3], iX[i][j]);
+                }
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                const float m = wave_max_f32(em[k]);
+                nsh[k] = m > -kInfF ? fmaxf(ceilf(m * kLog2e), -2000.f) : 0.f;
+            }
+        }
+
         double part[kNP];
 #pragma unroll
         for (int i = 0; i < kNP; ++i) part[i] = 0.0;
@@ -343,7 +393,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
 #pragma unroll
                     for (int j = 0; j < TY; ++j) {
                         const float q = env == 0 ? tn[i][j] : env == 1 ? tX[i][j] : env == 2 ? in_[i][j] : iX[i][j];
-                        f[j] = __builtin_amdgcn_exp2f(q * kLog2e);
+                        f[j] = __builtin_amdgcn_exp2f(fmaf(q, kLog2e, -nsh[env]));
                     }
                     const float4_t c = mfma_ystage<KS, CT>(f, yb);
                     __builtin_amdgcn_sched_barrier(0);
@@ -370,6 +420,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                     }
                 }
             }
+        }
+        if (CT != KBL_PREC_MIXED_FP32) {
+            // back to the element's log-peak scale (exact powers of two)
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                part[i] = ldexp(part[i], (int)nsh[0]);
+                part[6 + i] = ldexp(part[6 + i], (int)nsh[1]);
+            }
+            part[12] = ldexp(part[12], (int)nsh[2]);
+            part[13] = ldexp(part[13], (int)nsh[3]);
         }
         block_sum_t<NT, kNP>(part, red);
         if (tid == 0) {
