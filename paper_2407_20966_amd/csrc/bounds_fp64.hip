@@ -37,7 +37,8 @@ namespace {
 // tables built per sub-chunk of kTabStates states (fewer VALU ops, more LDS
 // traffic and barriers).
 template <int BX, int BY, int TX, int TY, int BTAB>
-__global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
+__global__ __launch_bounds__(BX * BY)
+__attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) void bounds_fp64_2d(BoundsArgs p) {
     constexpr int NT = BX * BY;
     constexpr int NXM = BX * TX;
     constexpr int NYM = BY * TY;
@@ -192,43 +193,71 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d(BoundsArgs p) {
         double cx = lox, cy = loy, dx = hx, dy = hy;
         int otx = tx, oty = ty;
         asm volatile("" : "+v"(cx), "+v"(cy), "+v"(dx), "+v"(dy), "+v"(otx), "+v"(oty));
+        // The weights and moment polynomials are separable, M = wx wy,
+        // |u|^2 / 2 = vx^2 / 2 + vy^2 / 2 and the sign of M u_k depends on
+        // u_k alone, so each node only feeds per-row sums over y (R: lower
+        // and upper envelope, internal parts) and per-column sums over x (C:
+        // lower and upper envelope), six fma per node; the moments are then
+        // formed once per row and once per column.
         double sr[2] = {0, 0}, se[2] = {0, 0};    // rho, E: (lower, upper) envelope sums
         double mn[2][2] = {{0, 0}, {0, 0}};       // [dir][0]: sum u<0 of M u g_max, [1]: u>=0, M u g_min
         double mx[2][2] = {{0, 0}, {0, 0}};       // [dir][0]: sum u<0 of M u g_min, [1]: u>=0, M u g_max
+        double ctn[TY], ctx[TY];                  // per column: sum over x of wx g_min, wx g_max
+#pragma unroll
+        for (int j = 0; j < TY; ++j) { ctn[j] = 0.0; ctx[j] = 0.0; }
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int jx = otx + BX * i;
             if (jx >= p.nx) continue;
             const double vx = node_pos(cx, jx, dx);
             const double wx = dx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+            double rtn = 0.0, rtx = 0.0, rin = 0.0, rix = 0.0;   // per row: sum over y of wy g
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
                 const int jy = oty + BY * j;
                 if (jy >= p.ny) continue;
-                const double vy = node_pos(cy, jy, dy);
-                const double M = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
+                const double wy = dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
                 const double gtn = exp_tab(qtn[i][j], sExp);
                 const double gtx = exp_tab(qtx[i][j], sExp);
                 const double gin = exp_tab(qin[i][j], sExp);
                 const double gix = exp_tab(qix[i][j], sExp);
-                const double hu2 = 0.5 * vx * vx + 0.5 * vy * vy;
-                sr[0] += M * gtn;
-                sr[1] += M * gtx;
-                se[0] += M * (hu2 * gtn + gin);
-                se[1] += M * (hu2 * gtx + gix);
-                const double mu[2] = {M * vx, M * vy};
-#pragma unroll
-                for (int d = 0; d < 2; ++d) {
-                    const double neg = fmin(mu[d], 0.0), pos = fmax(mu[d], 0.0);
-                    mn[d][0] += neg * gtx;
-                    mn[d][1] += pos * gtn;
-                    mx[d][0] += neg * gtn;
-                    mx[d][1] += pos * gtx;
-                }
+                rtn = fma(wy, gtn, rtn);
+                rtx = fma(wy, gtx, rtx);
+                rin = fma(wy, gin, rin);
+                rix = fma(wy, gix, rix);
+                ctn[j] = fma(wx, gtn, ctn[j]);
+                ctx[j] = fma(wx, gtx, ctx[j]);
                 // one node at a time: keeps the exp temporaries of different
                 // nodes from being interleaved (register pressure)
                 __builtin_amdgcn_sched_barrier(0);
             }
+            const double hx2 = 0.5 * vx * vx;
+            sr[0] = fma(wx, rtn, sr[0]);
+            sr[1] = fma(wx, rtx, sr[1]);
+            se[0] = fma(wx, fma(hx2, rtn, rin), se[0]);
+            se[1] = fma(wx, fma(hx2, rtx, rix), se[1]);
+            const double mu = wx * vx;
+            const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+            mn[0][0] = fma(neg, rtx, mn[0][0]);
+            mn[0][1] = fma(pos, rtn, mn[0][1]);
+            mx[0][0] = fma(neg, rtn, mx[0][0]);
+            mx[0][1] = fma(pos, rtx, mx[0][1]);
+        }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int jy = oty + BY * j;
+            if (jy >= p.ny) continue;
+            const double vy = node_pos(cy, jy, dy);
+            const double wy = dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
+            const double wy2 = wy * (0.5 * vy * vy);
+            se[0] = fma(wy2, ctn[j], se[0]);
+            se[1] = fma(wy2, ctx[j], se[1]);
+            const double mu = wy * vy;
+            const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+            mn[1][0] = fma(neg, ctx[j], mn[1][0]);
+            mn[1][1] = fma(pos, ctn[j], mn[1][1]);
+            mx[1][0] = fma(neg, ctn[j], mx[1][0]);
+            mx[1][1] = fma(pos, ctx[j], mx[1][1]);
         }
         double part[8] = {rm * sr[0], rp * sr[1], rm * se[0], rp * se[1],
                           rp * mn[0][0] + rm * mn[0][1], rm * mx[0][0] + rp * mx[0][1],
