@@ -318,20 +318,27 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
             for (int i = 0; i < TX; ++i)
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
-                    const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
-                    const double d2 = dx * dx + dy * dy;
+                    // the node's shares won by s: distribution envelopes (wt)
+                    // and internal ones (wi), selected by a 0/1 factor (the
+                    // shares are finite: M = 0 outside the grid)
+                    double wt = 0.0, wi = 0.0;
 #pragma unroll
                     for (int env = 0; env < 4; ++env) {
                         const bool m = wn[env][i][j] == s;
-                        const double wf = m ? q[env][i][j] : 0.0;
-                        z[0] += wf;
-                        z[1] = fma(wf, dx, z[1]);
-                        if (D == 2) z[2] = fma(wf, dy, z[2]);
-                        z[3] = fma(wf, d2, z[3]);
-                        if (env >= 2) z[4] += wf;
+                        const double sel = m ? 1.0 : 0.0;
+                        if (env < 2) wt = fma(sel, q[env][i][j], wt);
+                        else         wi = fma(sel, q[env][i][j], wi);
                         wn[env][i][j] = m ? kNoKey : wn[env][i][j];
                         nlk = min(nlk, wn[env][i][j]);
                     }
+                    const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
+                    const double d2 = dx * dx + dy * dy;
+                    const double wf = wt + wi;
+                    z[0] += wf;
+                    z[1] = fma(wf, dx, z[1]);
+                    if (D == 2) z[2] = fma(wf, dy, z[2]);
+                    z[3] = fma(wf, d2, z[3]);
+                    z[4] += wi;
                 }
             lk = nlk;
             double zz[8] = {z[0], z[1], z[2], z[3], z[4], 0.0, 0.0, 0.0};
