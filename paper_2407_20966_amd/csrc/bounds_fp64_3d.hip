@@ -181,42 +181,101 @@ void bounds_fp64_3d(BoundsArgs p) {
             for (int j = 0; j < TY; ++j) uy[j] = node_pos(cy, oty + BY * j, dy);
 #pragma unroll
             for (int k = 0; k < TZ; ++k) uz[k] = node_pos(cz, z0 + otz + BZ * k, dz);
-            double part[10] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+            // Separable contraction: M = wx wy wz, |u|^2 / 2 splits by
+            // direction and the sign of M u_k is the sign of u_k, so each node
+            // feeds the marginal sums over the other two directions (X per x
+            // row, Y per y column, Z per z plane; lower and upper envelope)
+            // and the internal parts; the moments are formed from the
+            // marginals once per row, column and plane.  The factors (1 -+ r)
+            // of eq. relaxed are applied to the sums.
+            double xs[2] = {0, 0}, xe[2] = {0, 0}, xm[2][2] = {{0, 0}, {0, 0}};   // from X
+            double yt[TY][2], zt[TZ][2], ie[2] = {0, 0};
+#pragma unroll
+            for (int j = 0; j < TY; ++j) { yt[j][0] = 0.0; yt[j][1] = 0.0; }
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) { zt[k][0] = 0.0; zt[k][1] = 0.0; }
 #pragma unroll
             for (int i = 0; i < TX; ++i) {
                 const int jx = otx + BX * i;
                 if (jx >= p.nx) continue;
                 const double wx = dx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+                double xt[2] = {0, 0};
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
                     const int jy = oty + BY * j;
                     if (jy >= p.ny) continue;
-                    const double wxy = wx * (dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
+                    const double wy = dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
+                    const double wxy = wx * wy;
 #pragma unroll
                     for (int k = 0; k < TZ; ++k) {
                         const int jz = z0 + otz + BZ * k;
                         if (jz >= p.nz) continue;
-                        const double M = wxy * (dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0));
-                        const double ftn = rm * exp_tab(qtn[i][j][k], sExp);
-                        const double ftx = rp * exp_tab(qtx[i][j][k], sExp);
-                        const double fin = rm * exp_tab(qin[i][j][k], sExp);
-                        const double fix = rp * exp_tab(qix[i][j][k], sExp);
-                        const double hu2 = 0.5 * ux[i] * ux[i] + 0.5 * uy[j] * uy[j] + 0.5 * uz[k] * uz[k];
-                        part[0] += M * ftn;
-                        part[1] += M * ftx;
-                        part[2] += M * (hu2 * ftn + fin);
-                        part[3] += M * (hu2 * ftx + fix);
-                        if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
-                        else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
-                        if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
-                        else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
-                        if (uz[k] < 0.0) { part[8] += M * uz[k] * ftx; part[9] += M * uz[k] * ftn; }
-                        else             { part[8] += M * uz[k] * ftn; part[9] += M * uz[k] * ftx; }
+                        const double wz = dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0);
+                        const double gtn = exp_tab(qtn[i][j][k], sExp);
+                        const double gtx = exp_tab(qtx[i][j][k], sExp);
+                        const double gin = exp_tab(qin[i][j][k], sExp);
+                        const double gix = exp_tab(qix[i][j][k], sExp);
+                        const double wyz = wy * wz, wxz = wx * wz, M = wxy * wz;
+                        xt[0] = fma(wyz, gtn, xt[0]);
+                        xt[1] = fma(wyz, gtx, xt[1]);
+                        yt[j][0] = fma(wxz, gtn, yt[j][0]);
+                        yt[j][1] = fma(wxz, gtx, yt[j][1]);
+                        zt[k][0] = fma(wxy, gtn, zt[k][0]);
+                        zt[k][1] = fma(wxy, gtx, zt[k][1]);
+                        ie[0] = fma(M, gin, ie[0]);
+                        ie[1] = fma(M, gix, ie[1]);
                         // one node at a time (register pressure)
                         __builtin_amdgcn_sched_barrier(0);
                     }
                 }
+                const double h2 = 0.5 * ux[i] * ux[i], mu = wx * ux[i];
+                const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    xs[b] = fma(wx, xt[b], xs[b]);
+                    xe[b] = fma(wx * h2, xt[b], xe[b]);
+                }
+                xm[0][0] = fma(neg, xt[1], xm[0][0]);   // u < 0, upper envelope
+                xm[0][1] = fma(pos, xt[0], xm[0][1]);   // u >= 0, lower envelope
+                xm[1][0] = fma(neg, xt[0], xm[1][0]);   // u < 0, lower envelope
+                xm[1][1] = fma(pos, xt[1], xm[1][1]);   // u >= 0, upper envelope
             }
+            // y and z moments from the column and plane marginals
+            double ye[2] = {0, 0}, ym[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+            for (int j = 0; j < TY; ++j) {
+                const int jy = oty + BY * j;
+                if (jy >= p.ny) continue;
+                const double wy = dy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
+                const double h2 = 0.5 * uy[j] * uy[j], mu = wy * uy[j];
+                const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) ye[b] = fma(wy * h2, yt[j][b], ye[b]);
+                ym[0][0] = fma(neg, yt[j][1], ym[0][0]);
+                ym[0][1] = fma(pos, yt[j][0], ym[0][1]);
+                ym[1][0] = fma(neg, yt[j][0], ym[1][0]);
+                ym[1][1] = fma(pos, yt[j][1], ym[1][1]);
+            }
+            double ze[2] = {0, 0}, zm[2][2] = {{0, 0}, {0, 0}};
+#pragma unroll
+            for (int k = 0; k < TZ; ++k) {
+                const int jz = z0 + otz + BZ * k;
+                if (jz >= p.nz) continue;
+                const double wz = dz * ((jz == 0 || jz == p.nz - 1) ? 0.5 : 1.0);
+                const double h2 = 0.5 * uz[k] * uz[k], mu = wz * uz[k];
+                const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+#pragma unroll
+                for (int b = 0; b < 2; ++b) ze[b] = fma(wz * h2, zt[k][b], ze[b]);
+                zm[0][0] = fma(neg, zt[k][1], zm[0][0]);
+                zm[0][1] = fma(pos, zt[k][0], zm[0][1]);
+                zm[1][0] = fma(neg, zt[k][0], zm[1][0]);
+                zm[1][1] = fma(pos, zt[k][1], zm[1][1]);
+            }
+            double part[10] = {rm * xs[0], rp * xs[1],
+                               rm * (xe[0] + ye[0] + ze[0] + ie[0]), rp * (xe[1] + ye[1] + ze[1] + ie[1]),
+                               rp * xm[0][0] + rm * xm[0][1], rm * xm[1][0] + rp * xm[1][1],
+                               rp * ym[0][0] + rm * ym[0][1], rm * ym[1][0] + rp * ym[1][1],
+                               rp * zm[0][0] + rm * zm[0][1], rm * zm[1][0] + rp * zm[1][1]};
             block_sum_t<NT, 10>(part, red);
             if (tid == 0) {
 #pragma unroll
