@@ -385,28 +385,58 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
             }
         }
 
-        double part[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        // separable contraction (M = wx wy; the sign of M u_k is the sign of
+        // u_k): each node feeds per-row sums over y and per-column sums over
+        // x, the moments are formed once per row and column, and (1 -+ r) is
+        // applied to the sums
+        double sr[2] = {0, 0}, se[2] = {0, 0}, mxs[2][2] = {{0, 0}, {0, 0}}, mys[2][2] = {{0, 0}, {0, 0}};
+        double cn[TY], cx[TY];   // per column: sum over x of wx g_min, wx g_max
+#pragma unroll
+        for (int j = 0; j < TY; ++j) { cn[j] = 0.0; cx[j] = 0.0; }
 #pragma unroll
         for (int i = 0; i < TX; ++i) {
             const int jx = tx + BX * i;
             if (jx >= p.nx) continue;
             const double wx = hx * ((jx == 0 || jx == p.nx - 1) ? 0.5 : 1.0);
+            double rn = 0.0, rx = 0.0, ren = 0.0, rex = 0.0;   // per row: sum over y of wy g, wy e
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
                 const int jy = ty + BY * j;
                 if (jy >= p.ny) continue;
-                const double M = wx * (hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0));
-                const double ftn = rm * gn[i][j], ftx = rp * gx[i][j];
-                part[0] += M * ftn;
-                part[1] += M * ftx;
-                part[2] += M * (rm * en[i][j]);
-                part[3] += M * (rp * ex[i][j]);
-                if (ux[i] < 0.0) { part[4] += M * ux[i] * ftx; part[5] += M * ux[i] * ftn; }
-                else             { part[4] += M * ux[i] * ftn; part[5] += M * ux[i] * ftx; }
-                if (uy[j] < 0.0) { part[6] += M * uy[j] * ftx; part[7] += M * uy[j] * ftn; }
-                else             { part[6] += M * uy[j] * ftn; part[7] += M * uy[j] * ftx; }
+                const double wy = hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
+                rn = fma(wy, gn[i][j], rn);
+                rx = fma(wy, gx[i][j], rx);
+                ren = fma(wy, en[i][j], ren);
+                rex = fma(wy, ex[i][j], rex);
+                cn[j] = fma(wx, gn[i][j], cn[j]);
+                cx[j] = fma(wx, gx[i][j], cx[j]);
             }
+            sr[0] = fma(wx, rn, sr[0]);
+            sr[1] = fma(wx, rx, sr[1]);
+            se[0] = fma(wx, ren, se[0]);
+            se[1] = fma(wx, rex, se[1]);
+            const double mu = wx * ux[i];
+            const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+            mxs[0][0] = fma(neg, rx, mxs[0][0]);   // lower bound: u < 0 takes g_max
+            mxs[0][1] = fma(pos, rn, mxs[0][1]);   //              u >= 0 takes g_min
+            mxs[1][0] = fma(neg, rn, mxs[1][0]);   // upper bound: u < 0 takes g_min
+            mxs[1][1] = fma(pos, rx, mxs[1][1]);   //              u >= 0 takes g_max
         }
+#pragma unroll
+        for (int j = 0; j < TY; ++j) {
+            const int jy = ty + BY * j;
+            if (jy >= p.ny) continue;
+            const double wy = hy * ((jy == 0 || jy == p.ny - 1) ? 0.5 : 1.0);
+            const double mu = wy * uy[j];
+            const double neg = fmin(mu, 0.0), pos = fmax(mu, 0.0);
+            mys[0][0] = fma(neg, cx[j], mys[0][0]);
+            mys[0][1] = fma(pos, cn[j], mys[0][1]);
+            mys[1][0] = fma(neg, cn[j], mys[1][0]);
+            mys[1][1] = fma(pos, cx[j], mys[1][1]);
+        }
+        double part[8] = {rm * sr[0], rp * sr[1], rm * se[0], rp * se[1],
+                          rp * mxs[0][0] + rm * mxs[0][1], rm * mxs[1][0] + rp * mxs[1][1],
+                          rp * mys[0][0] + rm * mys[0][1], rm * mys[1][0] + rp * mys[1][1]};
         block_sum_t<NT, 8>(part, red);
         if (tid == 0) store_bounds<2>(p, e, part, flags);
     }
