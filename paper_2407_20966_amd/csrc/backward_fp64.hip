@@ -393,9 +393,13 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
     }
 }
 
-// dJ/dstates[v][node] = sum over the elements e of the stencil row of the
-// node's element J (stencils are symmetric: J's row lists every element whose
-// stencil holds J) of the slot of J in row e.  Fixed CSR order: deterministic.
+// dJ/dstates[v][node] = sum over the distinct elements e of the stencil row of
+// the node's element J (stencils are symmetric: J's row lists every element
+// whose stencil holds J) of the slot of J's first entry in row e.  An element
+// listed twice in J's row (e.g. the left and right neighbour of a periodic
+// mesh two elements wide) is counted once; a repeated entry of J in row e
+// holds zero shares, since the first entry in stencil order wins every tie.
+// Fixed CSR order: deterministic.
 template <int D>
 __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* slot, double* gst) {
     constexpr int NV = D + 2;
@@ -411,6 +415,9 @@ __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* 
             for (int64_t r = r0; r < r1; ++r) {
                 const int32_t e = p.cols[r];
                 if (e < 0 || e >= p.n_elem) continue;
+                bool seen = false;
+                for (int64_t q = r0; q < r && !seen; ++q) seen = p.cols[q] == e;
+                if (seen) continue;
                 const int64_t q0 = p.rowptr[e], q1 = p.rowptr[e + 1];
                 if (q0 < 0 || q1 <= q0 || q1 > p.nnz) continue;
                 for (int64_t k = q0; k < q1; ++k) {

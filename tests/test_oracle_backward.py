@@ -102,3 +102,40 @@ def test_pressure_step_gradient():
     _, _, st = oracle.workload_limit(wl, b)
     assert (st & oracle.ST_PSTEP).any()
     fd_check(wl, "solution", n_dofs=40, seed=3)
+
+
+
+def _dedup_rows(rowptr, cols):
+    rp, cl = [0], []
+    for e in range(rowptr.size - 1):
+        seen = []
+        for c in cols[rowptr[e]:rowptr[e + 1]]:
+            if c not in seen:
+                seen.append(int(c))
+        cl.extend(seen)
+        rp.append(len(cl))
+    return np.array(rp, dtype=np.int32), np.array(cl, dtype=np.int32)
+
+
+@pytest.mark.parametrize("N,seed", [(1, 41), (2, 40)])
+def test_duplicate_stencil_entries(N, seed):
+    """Periodic meshes one or two elements wide list the same neighbour more
+    than once in a stencil row (left = right, down = up).  The bounds depend
+    on the set of stencil states only (eq. fminmax takes min/max over the
+    states), so the gradient with the repeated entries must equal the one
+    with each row reduced to distinct entries; finite differences of the
+    forward pin it too."""
+    wl = synth.make_quad_workload(N=N, seed=seed, grid_nodes=20, name=f"fd_dup{N}")
+    row = wl.cols[wl.rowptr[0]:wl.rowptr[1]]
+    assert len(np.unique(row)) < len(row)
+    wl.target = wl.states + 20.0 * (wl.target - wl.states)
+    G = np.random.default_rng(seed).standard_normal(wl.target.shape)
+    gsol, gst, gb = oracle.workload_backward(wl, G)
+    rp, cl = _dedup_rows(wl.rowptr, wl.cols)
+    g = wl.grid
+    gsol1, gst1, gb1 = oracle.backward(wl.dim, wl.gamma, wl.states, rp, cl, wl.n_s, g.mode,
+                                       g.n[:2], g.lo, g.hi, g.k, wl.r_fac, wl.target,
+                                       wl.node_weights, G)
+    for a, b in ((gsol, gsol1), (gst, gst1), (gb, gb1)):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * np.abs(b).max())
+    fd_check(wl, "states", n_dofs=30, seed=N)
