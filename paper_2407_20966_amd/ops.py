@@ -70,6 +70,17 @@ def _check(t: torch.Tensor, name: str, dtype: torch.dtype, device=None):
         raise ValueError(f"{name} must be contiguous")
 
 
+def _out(t: Optional[torch.Tensor], name: str, dtype: torch.dtype, device, shape):
+    """A caller-supplied output tensor, checked like an input and for its exact
+    shape (the kernels write every entry of it), or a new one."""
+    if t is None:
+        return torch.empty(shape, dtype=dtype, device=device)
+    _check(t, name, dtype, device)
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
 def compute_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tensor, n_s: int,
                    vgrid: L.VGrid, params: L.Params, out: Optional[torch.Tensor] = None,
                    status: Optional[torch.Tensor] = None,
@@ -83,18 +94,8 @@ def compute_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tenso
     n_elem = rowptr.numel() - 1
     if states.dim() != 2 or states.shape[1] != n_elem * n_s:
         raise ValueError(f"states must be [d+2, n_elem*n_s] = [*, {n_elem * n_s}], got {tuple(states.shape)}")
-    if out is None:
-        out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
-    else:
-        _check(out, "out", torch.float64, dev)
-        if tuple(out.shape) != (2 * (dim + 2), n_elem):
-            raise ValueError("out has the wrong shape")
-    if status is None:
-        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
-    else:
-        _check(status, "status", torch.int32, dev)
-        if status.numel() != n_elem:
-            raise ValueError("status has the wrong size")
+    out = _out(out, "out", torch.float64, dev, (2 * (dim + 2), n_elem))
+    status = _out(status, "status", torch.int32, dev, (n_elem,))
     rc = L.lib().kbl_compute_bounds(C.byref(params), dim, n_elem, int(n_s), cols.numel(),
                                     _ptr(states), _ptr(rowptr), _ptr(cols), C.byref(vgrid),
                                     _ptr(out), _ptr(status), _stream(dev, stream))
@@ -116,14 +117,10 @@ def compute_bounds_nodes(states: torch.Tensor, rowptr: torch.Tensor, cols: torch
     _check(cols, "cols", torch.int32, dev)
     dim = states.shape[0] - 2
     n_elem = rowptr.numel() - 1
-    if out is None:
-        out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
-    else:
-        _check(out, "out", torch.float64, dev)
-        if tuple(out.shape) != (2 * (dim + 2), n_elem):
-            raise ValueError("out has the wrong shape")
-    if status is None:
-        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    if states.dim() != 2:
+        raise ValueError("states must be [d+2, n_nodes]")
+    out = _out(out, "out", torch.float64, dev, (2 * (dim + 2), n_elem))
+    status = _out(status, "status", torch.int32, dev, (n_elem,))
     rc = L.lib().kbl_compute_bounds_nodes(C.byref(params), dim, n_elem, states.shape[1],
                                           cols.numel(), _ptr(states), _ptr(rowptr), _ptr(cols),
                                           C.byref(vgrid), _ptr(out), _ptr(status),
@@ -150,10 +147,18 @@ def riemann_states(states: torch.Tensor, node_i: torch.Tensor, node_j: torch.Ten
         raise ValueError("node_j/normals do not match node_i")
     if lam is not None:
         _check(lam, "lam", torch.float64, dev)
+        if lam.numel() != n_pairs:
+            raise ValueError("lam must have one entry per pair")
     n_elem = 0
+    if (bounds is None) != (elem is None):
+        raise ValueError("bounds and elem go together")
     if bounds is not None:
         _check(bounds, "bounds", torch.float64, dev)
         _check(elem, "elem", torch.int32, dev)
+        if bounds.dim() != 2 or bounds.shape[0] != 2 * (dim + 2):
+            raise ValueError(f"bounds must be [2(d+2), n_elem] = [{2 * (dim + 2)}, *]")
+        if elem.numel() != n_pairs:
+            raise ValueError("elem must have one entry per pair")
         n_elem = bounds.shape[1]
     bar = torch.empty((dim + 2, n_pairs), dtype=torch.float64, device=dev)
     status = torch.empty(n_pairs, dtype=torch.int32, device=dev)
@@ -173,8 +178,12 @@ def autotune_bounds(states: torch.Tensor, rowptr: torch.Tensor, cols: torch.Tens
     the fastest for this problem shape (see kbl_autotune_bounds).  Synchronises."""
     _check(states, "states", torch.float64)
     dev = states.device
+    _check(rowptr, "rowptr", torch.int32, dev)
+    _check(cols, "cols", torch.int32, dev)
     dim = states.shape[0] - 2
     n_elem = rowptr.numel() - 1
+    if states.dim() != 2 or states.shape[1] != n_elem * n_s:
+        raise ValueError(f"states must be [d+2, n_elem*n_s] = [*, {n_elem * n_s}]")
     out = torch.empty((2 * (dim + 2), n_elem), dtype=torch.float64, device=dev)
     status = torch.empty(n_elem, dtype=torch.int32, device=dev)
     idx = L.lib().kbl_autotune_bounds(C.byref(params), dim, n_elem, int(n_s), cols.numel(),
@@ -195,20 +204,17 @@ def limit(solution: torch.Tensor, bounds: torch.Tensor, node_weights, n_s: int,
     dev = solution.device
     _check(bounds, "bounds", torch.float64, dev)
     dim = solution.shape[0] - 2
+    if solution.dim() != 2 or bounds.dim() != 2:
+        raise ValueError("solution and bounds must be 2D")
     n_elem = bounds.shape[1]
     if solution.shape[1] != n_elem * n_s or bounds.shape[0] != 2 * (dim + 2):
         raise ValueError("solution/bounds shapes do not match n_s and the dimension")
     w = torch.as_tensor(node_weights, dtype=torch.float64).cpu().contiguous()
     if w.numel() != n_s:
         raise ValueError("node_weights must have n_s entries")
-    if out is None:
-        out = torch.empty_like(solution)
-    else:
-        _check(out, "out", torch.float64, dev)
-    if alpha is None:
-        alpha = torch.empty((2, n_elem), dtype=torch.float64, device=dev)
-    if status is None:
-        status = torch.empty(n_elem, dtype=torch.int32, device=dev)
+    out = _out(out, "out", torch.float64, dev, tuple(solution.shape))
+    alpha = _out(alpha, "alpha", torch.float64, dev, (2, n_elem))
+    status = _out(status, "status", torch.int32, dev, (n_elem,))
     rc = L.lib().kbl_limit(C.byref(params), dim, n_elem, int(n_s), _ptr(solution), _ptr(bounds),
                            C.c_void_p(w.data_ptr()), _ptr(out), _ptr(alpha), _ptr(status),
                            _stream(dev, stream))
@@ -240,6 +246,8 @@ def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torc
     _check(cols, "cols", torch.int32, dev)
     dim = states.shape[0] - 2
     n_elem = rowptr.numel() - 1
+    if states.dim() != 2 or states.shape[1] != n_elem * n_s:
+        raise ValueError(f"states must be [d+2, n_elem*n_s] = [*, {n_elem * n_s}]")
     if (fwd_bounds is None) != (fwd_status is None):
         raise ValueError("fwd_bounds and fwd_status go together")
     if fwd_bounds is not None:
@@ -262,6 +270,20 @@ def bounds_limit_backward(states: torch.Tensor, rowptr: torch.Tensor, cols: torc
     if rc != L.KBL_OK:
         raise L.KblError(rc, "kbl_bounds_limit_backward")
     return gst, gsol, gb, status
+
+
+def status_summary(status: torch.Tensor, out: Optional[torch.Tensor] = None,
+                   stream=None) -> torch.Tensor:
+    """Per-bit counts [32] (int64) of a status tensor (see kbl_status_summary);
+    enqueued on the stream, no host synchronisation."""
+    _check(status, "status", torch.int32)
+    dev = status.device
+    out = _out(out, "out", torch.int64, dev, (32,))
+    rc = L.lib().kbl_status_summary(_ptr(status), status.numel(), _ptr(out),
+                                    _stream(dev, stream))
+    if rc != L.KBL_OK:
+        raise L.KblError(rc, "kbl_status_summary")
+    return out
 
 
 class KineticBoundsLimit(torch.autograd.Function):
