@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import glob
 import os
+from concurrent.futures import ThreadPoolExecutor
 import shutil
 import subprocess
 import sys
@@ -73,14 +74,18 @@ def _run(cmd, verbose):
 def build(verbose: bool = False, extra=()) -> str:
     objdir = os.path.join(ROOT, "_build", "kbl")
     os.makedirs(objdir, exist_ok=True)
-    objs = []
+    objs, cmds = [], []
     compile_flags = [f for f in HIP_FLAGS if f != "-shared"]
     for src in sources():
         obj = os.path.join(objdir, os.path.splitext(os.path.basename(src))[0] + ".o")
-        cmd = ([hipcc()] + compile_flags + SOURCE_FLAGS.get(os.path.basename(src), [])
-               + list(extra) + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src])
-        _run(cmd, verbose)
+        cmds.append([hipcc()] + compile_flags + SOURCE_FLAGS.get(os.path.basename(src), [])
+                    + list(extra) + ["-I", os.path.join(ROOT, "include"), "-c", "-o", obj, src])
         objs.append(obj)
+    # one translation unit per worker; every failure is raised
+    jobs = max(1, min(len(cmds), int(os.environ.get("MAX_JOBS", 0)) or os.cpu_count() or 1, 16))
+    with ThreadPoolExecutor(jobs) as pool:
+        for f in [pool.submit(_run, c, verbose) for c in cmds]:
+            f.result()
     out_tmp = LIB + ".tmp"
     _run([hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", out_tmp] + objs, verbose)
     os.replace(out_tmp, LIB)
