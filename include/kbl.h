@@ -313,6 +313,24 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
                                      double* grad_bounds, uint32_t* elem_status,
                                      void* workspace, size_t workspace_bytes, void* stream);
 
+/*
+ * kbl_status_summary - how many entries of a status array carry each bit:
+ * counts[b] = number of i < n with bit b of elem_status[i] set, for b = 0..31.
+ * Works on any array of KBL_ST_* words (kbl_compute_bounds, kbl_limit, the
+ * backward) or of the KBL_RS_* pair bits of kbl_riemann_states; it is the
+ * on-demand reduction of the per-element conditions of Sec. 3.4 and 3.8
+ * (epsilon rule, pressure step, alpha_P = 0, ...) that the calls themselves
+ * only flag, without a host synchronisation.
+ *   elem_status  [n] device status words (may be NULL when n == 0).
+ *   counts       out [32] device uint64, overwritten (zeros when n == 0).
+ * Enqueues two small launches on `stream` (clear, then count) and returns;
+ * allocates nothing.  KBL_ERR_ARG for n < 0, counts == NULL, or
+ * elem_status == NULL with n > 0.  The counts are exact and independent of
+ * scheduling.
+ */
+kbl_status kbl_status_summary(const uint32_t* elem_status, int64_t n, uint64_t* counts,
+                              void* stream);
+
 /* Human-readable text for a status code (static storage). */
 const char* kbl_status_string(kbl_status s);
 

@@ -16,7 +16,8 @@ from .fr1d import FR1D  # noqa: F401
 from .ops import (  # noqa: F401
     KineticBoundsLimit, autotune_bounds, bounds_and_limit, bounds_limit_backward,
     compute_bounds, compute_bounds_nodes, limit, make_params, make_vgrid, riemann_states,
+    status_summary,
 )
 
 __all__ = ["compute_bounds", "compute_bounds_nodes", "limit", "riemann_states", "autotune_bounds", "bounds_limit_backward", "bounds_and_limit",
-           "KineticBoundsLimit", "make_params", "make_vgrid", "KblError", "FR1D"]
+           "KineticBoundsLimit", "status_summary", "make_params", "make_vgrid", "KblError", "FR1D"]

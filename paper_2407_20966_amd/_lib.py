@@ -135,6 +135,8 @@ def _load():
                                                   C.POINTER(VGrid), P, P, P, P, P, P, P, P,
                                                   P, P, C.c_size_t, P]
         lib.kbl_bounds_limit_backward.restype = C.c_int
+        lib.kbl_status_summary.argtypes = [P, C.c_int64, P, P]
+        lib.kbl_status_summary.restype = C.c_int
         F = C.POINTER(Fr1dCfg)
         lib.kbl_fr1d_columns.argtypes = [F]
         lib.kbl_fr1d_columns.restype = C.c_int64

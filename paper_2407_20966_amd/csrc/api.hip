@@ -469,4 +469,11 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 
+kbl_status kbl_status_summary(const uint32_t* elem_status, int64_t n, uint64_t* counts,
+                              void* stream) {
+    if (n < 0 || !counts || (n > 0 && !elem_status)) return KBL_ERR_ARG;
+    hipError_t err = kbl::launch_status_summary(elem_status, n, counts, (hipStream_t)stream);
+    return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
 }  // extern "C"

@@ -105,6 +105,9 @@ hipError_t launch_riemann_fp64(const RiemannArgs& a, int dim, hipStream_t stream
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
                                   double* slot, double* grad_states, uint32_t* status, int dim,
                                   bool mixed, hipStream_t stream);
+// Per-bit counts of n status words into counts[32] (cleared first).
+hipError_t launch_status_summary(const uint32_t* st, int64_t n, uint64_t* counts,
+                                 hipStream_t stream);
 hipError_t launch_limit_bwd_fp64(const LimitArgs& a, int dim, const double* grad, double* gsol,
                                  double* gbnd, hipStream_t stream);
 

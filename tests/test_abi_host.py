@@ -31,7 +31,7 @@ def test_header_declares_expected_entry_points():
     for s in ("kbl_compute_bounds", "kbl_limit", "kbl_status_string", "kbl_version",
               "kbl_default_params", "kbl_bounds_limit_backward", "kbl_backward_workspace_bytes",
               "kbl_autotune_bounds", "kbl_autotune_clear", "kbl_compute_bounds_nodes",
-              "kbl_riemann_states"):
+              "kbl_riemann_states", "kbl_status_summary"):
         assert s in syms
 
 
@@ -382,3 +382,9 @@ def test_fr1d_step_and_limit_argument_errors(lib):
         assert fn(cfg=dirich, wsb=lib.kbl_fr1d_workspace_bytes(C.byref(dirich))) == L.KBL_ERR_ARG
     assert step(dt=0.0) == L.KBL_ERR_ARG
     assert step(dt=float("nan")) == L.KBL_ERR_ARG
+
+
+def test_status_summary_rejects_bad_arguments(lib):
+    assert lib.kbl_status_summary(FAKE, -1, FAKE, None) == L.KBL_ERR_ARG
+    assert lib.kbl_status_summary(FAKE, 10, None, None) == L.KBL_ERR_ARG
+    assert lib.kbl_status_summary(None, 10, FAKE, None) == L.KBL_ERR_ARG
