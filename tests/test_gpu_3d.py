@@ -71,7 +71,7 @@ def check(kbl, wl, elems=None, r_fac=None, independent=False, autotune=False, to
         nodes = (sel[:, None] * wl.n_s + np.arange(wl.n_s)[None, :]).ravel()
         scale = element_value_scale(wl, wl.target, sel)
         lerr, _ = limited_error(lim[:, nodes], rl, scale, wl.n_s)
-        assert lerr <= 10 * tol, f"limited error {lerr:.3e}"
+        assert lerr <= tol, f"limited error {lerr:.3e}"
         diff = ls[sel] != rls
         if diff.any():
             near = np.abs(ral[0] - 1.0) < 1e-9

@@ -149,14 +149,14 @@ def test_mixed_limiter_end_to_end(kbl):
     tg = torch.from_numpy(wl.target).to(dev)
     prm = kbl.make_params(wl.gamma)
     out = {}
-    for prec in (0, 2, 1):
+    for prec in (0, 3, 2, 1):
         b, _ = gpu_bounds(kbl, wl, prec)
         lim, al, st = kbl.limit(tg, torch.from_numpy(b).to(dev), wl.node_weights, wl.n_s, prm)
         torch.cuda.synchronize()
         out[prec] = (b, lim.cpu().numpy(), st.cpu().numpy().view(np.uint32))
     nv, n_s = 4, wl.n_s
     c = wl.node_weights / wl.node_weights.sum()
-    for prec in (2, 1):
+    for prec in (3, 2, 1):
         b, lim, st = out[prec]
         L = lim.reshape(nv, wl.n_elem, n_s)
         T = wl.target.reshape(nv, wl.n_elem, n_s)
@@ -168,6 +168,53 @@ def test_mixed_limiter_end_to_end(kbl):
         lerr, _ = limited_error(lim, out[0][1], element_value_scale(wl, wl.target), n_s)
         print(f"[mixed] limited nodes, precision {prec} bounds vs FP64 bounds: {lerr:.2e} "
               f"(elements checked for feasibility: {ok.sum()}/{wl.n_elem})", flush=True)
+
+
+_WL_CACHE = {}
+
+
+def _workload(name):
+    if name not in _WL_CACHE:
+        _WL_CACHE.clear()            # keep one large workload alive at a time
+        _WL_CACHE[name] = synth.make_workload(name)
+    return _WL_CACHE[name]
+
+
+# limiter decisions that switch discontinuously (Sec. 3.4 epsilon rule,
+# Sec. 3.8 pressure step and alpha_P = 0): an element whose bounds sit within
+# the mixed tolerance of such a threshold may take the other branch
+BRANCH_BITS = np.uint32(0x4 | 0x10 | 0x20)
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("name,n_sample", [("quad256", 160), ("quad1024_sine", 96),
+                                           ("tri2m", 128)])
+def test_mixed_limited_vs_oracle(kbl, name, n_sample, prec):
+    """End to end: mixed bounds -> FP64 limiter on the GPU against oracle
+    bounds -> oracle limiter (eq. alpha, eq. limiter, eq. pmin, eq. doublelimit),
+    node by node on a seeded element sample, at the mixed tolerance 1e-5
+    relative to the element's value scale."""
+    wl = _workload(name)
+    sel = synth.sample_elements(wl, n_sample)
+    b, _ = gpu_bounds(kbl, wl, PRECS[prec])
+    dev = torch.device("cuda:0")
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    lim, al, ls = kbl.limit(torch.from_numpy(wl.target).to(dev), torch.from_numpy(b).to(dev),
+                            wl.node_weights, wl.n_s, prm)
+    torch.cuda.synchronize()
+    lim, ls = lim.cpu().numpy(), ls.cpu().numpy().view(np.uint32)[sel]
+    rb, _ = oracle.workload_bounds(wl, elems=sel)
+    rl, ral, rls = oracle.workload_limit(wl, rb, elems=sel)
+    nodes = (sel[:, None] * wl.n_s + np.arange(wl.n_s)[None, :]).ravel()
+    scale = element_value_scale(wl, wl.target, sel)
+    _, err = limited_error(lim[:, nodes], rl, scale, wl.n_s)
+    ties = ((ls ^ rls) & BRANCH_BITS) != 0
+    worst = float(err[:, ~ties].max()) if (~ties).any() else 0.0
+    print(f"[mixed-limited] {name} {prec}: max err {worst:.2e} over {len(sel)} elements "
+          f"({int((ral[0] < 1).sum())} limited, {int(((rls & 0x10) != 0).sum())} p-steps), "
+          f"{int(ties.sum())} branch ties", flush=True)
+    assert ties.sum() <= max(1, len(sel) // 100)
+    assert worst <= TOL
 
 
 def test_mixed_determinism(kbl):

@@ -96,7 +96,7 @@ def check_fr(kbl, wl, elems=None):
     print(f"[variants] {wl.name}: node-stencil bounds err {err:.2e}, limited err {lerr:.2e}, "
           f"limited {(ral[0] < 1).sum()}/{len(sel)}", flush=True)
     assert err <= TOL
-    assert lerr <= 10 * TOL
+    assert lerr <= TOL
     return b
 
 
