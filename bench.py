@@ -1,12 +1,21 @@
 """Throughput of the kinetic bounds + limiter hot path on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload quad256] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--workload tri2m] [--no-cpu-baseline]
 
 One step = kbl_compute_bounds + kbl_limit over the whole workload, inputs
-already resident in HBM.  Prints ONE JSON line (rank 0) with the throughput
-in elements/s, the roofline of the dominant kernel (the bounds pass, bound by
-VALU issue) measured with HIP events on the launch stream, and the FP64 CPU
-oracle timed on a bounded element sample on the host cores.
+already resident in HBM.  The default workload is the largest one that the
+method is exercised on: 2,000,000 P2 triangles with uneven vertex-neighbour
+stencils and a 64 x 64 per-stencil velocity grid.  Prints ONE JSON line with
+- the FP64 throughput in elements/s (`value`) and the roofline of the
+  dominant kernel (the FP64 bounds pass, bound by VALU issue) measured with
+  HIP events on the launch stream;
+- the same step with each mixed-precision form of the bounds (FP32
+  envelopes; FP32 VALU, FP16 MFMA or BF16 MFMA contraction), each against
+  its own VALU ceiling, and the MFMA forms' matrix-core rate;
+- the FP64 and mixed steps on the 1024^2-quad workload with a global 64 x 64
+  grid, and the FP64 backward on the 512^2-quad workload;
+- the FP64 CPU oracle timed on a bounded element sample, on all host cores
+  and on one core.
 """
 
 from __future__ import annotations
@@ -40,9 +49,10 @@ WORKLOAD_TEXT = {
                 "+1% smooth perturbation"),
     "quad1024_sine": ("2D Euler gamma=1.4, 1024x1024 periodic quads, p=3, 80-state stencils, "
                       "64x64 global velocity grid on [-12,12]^2 sqrt(theta_max), sine + Sod-jump field"),
-    "tri2m": ("2D Euler gamma=1.4, 2,000,000 jittered P2 triangles (6 nodes), vertex-neighbour "
-              "stencils (4-16 elements), 64x64 per-stencil velocity grid (k=4), radial shock "
-              "rho ratio 1e3, p ratio 1e5"),
+    "tri2m": ("2D Euler gamma=1.4, 2,000,000 jittered P2 triangles (6 nodes) on a periodic "
+              "1000x1000 lattice, vertex-neighbour stencils (11-16 elements, CSR), 64x64 "
+              "per-stencil velocity grid (k=4), r_fac=1e-3, radial shock rho ratio 1e3, "
+              "p ratio 1e5 +1% smooth perturbation"),
     "quad512": ("2D Euler gamma=1.4, 512x512 periodic quads, p=3, 80-state stencils, 48x48 "
                 "per-stencil velocity grid (k=4), 4-quadrant Riemann field"),
     "line64": ("1D Euler gamma=1.4, 64 elements, p=3, 12-state stencils, 64-node global velocity "
@@ -115,7 +125,7 @@ def profiled_traffic(kernel: str, grid_threads: int, workload: str, dim: int):
 
 
 def pair_ops(dim: int) -> int:
-    """Algorithmic VALU lane-ops per (stencil state, velocity node) pair.
+    """Algorithmic VALU lane-ops per (stencil state, velocity node) pair, FP64.
 
     2D: the log-Maxwellian is separable, q = A[jx] + B[jy]: two adds (q and
     q + ln(theta delta/2)) and four running min/max.  3D: the same with
@@ -123,6 +133,25 @@ def pair_ops(dim: int) -> int:
     is not counted).  1D: sub, mul, fma, fma, then four min/max.
     """
     return 8 if dim == 1 else 6
+
+
+# Mixed precision (FP32 envelopes, 2D): the same two adds per pair, but the
+# four running extrema take two states per step with the three-input
+# v_min3_f32 / v_max3_f32, one issue slot per extremum and pair of states:
+# 2 + 4/2 = 4 issue slots per pair at the unpacked FP32 VALU rate.
+MIXED_PAIR_OPS = 4
+# Dense FP16/BF16 matrix-core peak of MI355X (no sparsity).
+MFMA_PEAK_FLOPS = 2.5e15
+
+
+def mfma_flops_issued(wl, precision: int, tile: int, kbl) -> float:
+    """Matrix-core flops one mixed bounds launch issues in its y-stage
+    contraction: per element, each x tile of 16 nodes and each of the four
+    envelopes runs KS k-steps of 16x16x16 MFMAs, 3 per k-step for the FP16
+    hi/lo split, 6 for the BF16 three-way split (8192 flops each)."""
+    txw, ks, nw = kbl._lib.MIXED_TILES[tile]
+    per_k = 3 if precision == kbl.PREC_MIXED_FP16 else 6
+    return float(wl.n_elem) * txw * nw * 4 * ks * per_k * 2 * 16 * 16 * 16
 
 
 def kernel_shape(kbl, dim, tuned, n_elem, n_cu):
@@ -139,11 +168,30 @@ def kernel_shape(kbl, dim, tuned, n_elem, n_cu):
     return f"bounds_fp64_3d<{bx}, {by}, {bz}, {tx}, {ty}, {tz}>", blocks * bx * by * bz
 
 
-def cpu_baseline(wl, target_s: float = 12.0):
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(wl, target_s: float = 12.0, one_core_s: float = 5.0):
     """The oracle (bounds + limit) on a seeded element sample of the workload,
-    sized to take about target_s of wall time on the host cores."""
+    sized to take about target_s of wall time on all host cores, then on one
+    core (OpenMP limited to one thread) for about one_core_s."""
+    import ctypes
     import oracle
     oracle.build(force=False)
+    oracle._load()
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")      # the OpenMP runtime liboracle links
+        gomp.omp_get_max_threads.restype = ctypes.c_int
+    except OSError:
+        gomp = None
     rng = np.random.default_rng(12345)
 
     def run(n):
@@ -153,20 +201,32 @@ def cpu_baseline(wl, target_s: float = 12.0):
         oracle.workload_limit(wl, rb, elems=sample)
         return time.perf_counter() - t0
 
-    # grow the calibration sample until it takes at least a second, then size
-    n, dt = 64, 0.0
-    while n < wl.n_elem:
-        dt = run(n)
-        if dt >= 1.0:
-            break
-        n = min(wl.n_elem, n * 4)
-    n = int(min(wl.n_elem, max(64, n * target_s / max(dt, 1e-6))))
-    dt = run(n)
-    cores = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
-    return {"value": n / dt, "unit": "elements/s", "cores": cores, "kind": "oracle",
-            "sample": f"{n} seeded random elements of the same workload (bounds + limit), "
-                      f"{dt:.1f} s wall, FP64 direct-form oracle (gcc -O2, OpenMP)"}
+    def sized(target):
+        # grow the calibration sample until it takes at least 0.5 s, then size
+        n, dt = 16, 0.0
+        while n < wl.n_elem:
+            dt = run(n)
+            if dt >= 0.5:
+                break
+            n = min(wl.n_elem, n * 4)
+        n = int(min(wl.n_elem, max(16, n * target / max(dt, 1e-6))))
+        return n, run(n)
 
+    threads = gomp.omp_get_max_threads() if gomp else (
+        int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0)))
+    n, dt = sized(target_s)
+    out = {"value": n / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
+           "sample": f"{n} seeded random elements of {wl.name} (bounds + limit), {dt:.1f} s wall "
+                     f"on {threads} threads, FP64 direct-form oracle (gcc -O2, OpenMP over "
+                     f"elements)",
+           "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    if gomp is not None:
+        gomp.omp_set_num_threads(1)
+        n1, dt1 = sized(one_core_s)
+        gomp.omp_set_num_threads(threads)
+        out["one_core"] = {"value": n1 / dt1, "unit": "elements/s", "cores": 1,
+                           "sample": f"{n1} seeded random elements, {dt1:.1f} s wall"}
+    return out
 
 
 def _time_events(torch, stream, fn, steps, warmup):
@@ -390,18 +450,231 @@ def time_fr1d(args, kbl, torch, stream):
             "launches_per_step": 14}
 
 
+class Dev:
+    """A workload's inputs resident on the device, and output buffers."""
+
+    def __init__(self, kbl, torch, wl, dev):
+        g = wl.grid
+        self.wl = wl
+        self.st = torch.from_numpy(wl.states).to(dev)
+        self.rp = torch.from_numpy(wl.rowptr).to(dev)
+        self.cl = torch.from_numpy(wl.cols).to(dev)
+        self.tg = torch.from_numpy(wl.target).to(dev)
+        self.vg = kbl.make_vgrid(g.mode, g.n[: wl.dim], g.lo, g.hi, g.k)
+        self.bounds = torch.empty((2 * (wl.dim + 2), wl.n_elem), dtype=torch.float64, device=dev)
+        self.bstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+        self.lim = torch.empty_like(self.tg)
+        self.alpha = torch.empty((2, wl.n_elem), dtype=torch.float64, device=dev)
+        self.lstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
+
+
+def time_step(kbl, torch, d, prm_b, prm_l, stream, steps, warmup):
+    """One step = bounds + limit, timed over `steps` after `warmup`: wall ms
+    per step (host clock around synchronisations) and the average bounds and
+    limit launch times (HIP events recorded on the launch stream)."""
+    wl = d.wl
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        kbl.compute_bounds(d.st, d.rp, d.cl, wl.n_s, d.vg, prm_b, out=d.bounds, status=d.bstat,
+                           stream=stream)
+        if ev is not None:
+            ev[1].record(stream)
+        kbl.limit(d.tg, d.bounds, wl.node_weights, wl.n_s, prm_l, out=d.lim, alpha=d.alpha,
+                  status=d.lstat, stream=stream)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    wall = 1e3 * (time.perf_counter() - t0) / steps
+    b_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
+    l_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
+    return wall, b_ms, l_ms
+
+
+def autotune(args, kbl, d, prm, stream, label, sample=65536):
+    """Untimed: picks the tile and launch shape for this problem shape."""
+    if args.no_autotune:
+        return None
+    wl = d.wl
+    c = kbl.autotune_bounds(d.st, d.rp, d.cl, wl.n_s, d.vg, prm, sample_elems=sample,
+                            stream=stream)
+    t = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
+    print(f"[bench] autotuned {label}: {t}", file=sys.stderr, flush=True)
+    return t
+
+
+def limit_hbm_frac(d, l_ms):
+    """Limiter launch against HBM peak: solution read, limited solution,
+    bounds, alpha and status written or read once."""
+    wl = d.wl
+    byts = 2 * wl.target.nbytes + d.bounds.numel() * 8 + d.alpha.numel() * 8 + d.lstat.numel() * 4
+    return byts / (l_ms * 1e-3) / HBM_PEAK
+
+
+def fp64_leg(args, kbl, torch, d, stream, n_cu, label, steps):
+    """FP64 step on one workload: throughput and the bounds kernel's roofline."""
+    wl = d.wl
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    tuned = autotune(args, kbl, d, prm, stream, f"{label} fp64")
+    ms, b_ms, l_ms = time_step(kbl, torch, d, prm, prm, stream, steps, args.warmup)
+    print(f"[bench] {label} fp64: {ms:.3f} ms/step (bounds {b_ms:.3f} ms, limit {l_ms:.3f} ms)",
+          file=sys.stderr, flush=True)
+    ops = wl.pairs() * pair_ops(wl.dim)
+    achieved = ops / (b_ms * 1e-3)
+    kname, grid_threads = kernel_shape(kbl, wl.dim, tuned, wl.n_elem, n_cu)
+    traffic, traffic_grid = (profiled_traffic(kname, grid_threads, wl.name, wl.dim)
+                             if grid_threads else (None, None))
+    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
+            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
+            "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_FILE,
+            "traffic_grid_threads": traffic_grid, "kernel": kname, "grid_threads": grid_threads,
+            "ops_per_launch": ops, "pairs_per_launch": wl.pairs(),
+            "ops_per_pair": pair_ops(wl.dim), "kernel_ms": b_ms, "limit_ms": l_ms,
+            "limit_hbm_frac": limit_hbm_frac(d, l_ms)}
+    return {"ms_per_step": ms, "value": wl.n_elem / (ms * 1e-3), "unit": "elements/s",
+            "bounds_ms": b_ms, "limit_ms": l_ms, "launch": tuned, "roofline": roof,
+            "parity_tol": 1e-12}
+
+
+def mixed_legs(args, kbl, torch, d, stream, label, steps, ms_fp64, b_fp64):
+    """The same step with each mixed-precision form of the bounds (the
+    limiter stays FP64)."""
+    wl = d.wl
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    out = {}
+    for name, prec in (("fp32_valu", kbl.PREC_MIXED_FP32), ("fp16_mfma", kbl.PREC_MIXED_FP16),
+                       ("bf16_mfma", kbl.PREC_MIXED_BF16)):
+        prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=prec)
+        tuned = autotune(args, kbl, d, prm_m, stream, f"{label} {name}")
+        ms, b_ms, l_ms = time_step(kbl, torch, d, prm_m, prm, stream, steps, args.warmup)
+        ops = wl.pairs() * MIXED_PAIR_OPS
+        e = {"value": wl.n_elem / (ms * 1e-3), "unit": "elements/s", "ms_per_step": ms,
+             "bounds_ms": b_ms, "limit_ms": l_ms,
+             "roofline": {"bound": "alu", "achieved": ops / (b_ms * 1e-3) / 1e12,
+                          "peak": VALU_PEAK_OPS / 1e12, "unit": "TOP/s",
+                          "frac": ops / (b_ms * 1e-3) / VALU_PEAK_OPS,
+                          "ops_per_pair": MIXED_PAIR_OPS},
+             "speedup_vs_fp64": ms_fp64 / ms, "bounds_speedup_vs_fp64": b_fp64 / b_ms,
+             "launch": tuned, "parity_tol": 1e-5}
+        if prec != kbl.PREC_MIXED_FP32:
+            tile = tuned["tile"] if tuned else None
+            if tile is None:
+                g = wl.grid.n
+                n = max(g[0], g[1])
+                tile = 0 if n <= 16 else 1 if n <= 32 else 3 if n <= 48 else 5
+            fl = mfma_flops_issued(wl, prec, tile, kbl)
+            e["mfma"] = {"flops_issued_per_launch": fl,
+                         "achieved": fl / (b_ms * 1e-3) / 1e12, "peak": MFMA_PEAK_FLOPS / 1e12,
+                         "unit": "TFLOP/s", "frac": fl / (b_ms * 1e-3) / MFMA_PEAK_FLOPS}
+        out[name] = e
+        print(f"[bench] {label} mixed {name}: {ms:.3f} ms/step (bounds {b_ms:.3f} ms, "
+              f"frac {e['roofline']['frac']:.3f})", file=sys.stderr, flush=True)
+    return out
+
+
+def backward_leg(args, kbl, torch, synth, stream, name="quad512"):
+    """The hand-written backward of bounds + limiter on the differentiation
+    workload, J = sum w rho_limited; the forward's bounds and status are
+    handed over (as the autograd Function does)."""
+    dev = torch.device("cuda:0")
+    print(f"[bench] generating {name}", file=sys.stderr, flush=True)
+    d = Dev(kbl, torch, synth.make_workload(name), dev)
+    wl = d.wl
+    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
+    autotune(args, kbl, d, prm, stream, f"{name} fp64")
+    steps = max(2, args.steps // 2)
+    ms_fwd, b_fwd, _ = time_step(kbl, torch, d, prm, prm, stream, steps, args.warmup)
+    G = torch.zeros_like(d.tg)
+    G[0] = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n_nodes)).to(dev)
+
+    def time_backward(p):
+        fb = torch.empty_like(d.bounds)
+        fs = torch.empty_like(d.bstat)
+        kbl.compute_bounds(d.st, d.rp, d.cl, wl.n_s, d.vg, p, out=fb, status=fs, stream=stream)
+
+        def bstep():
+            return kbl.bounds_limit_backward(d.st, d.rp, d.cl, wl.n_s, d.vg, p, d.tg,
+                                             wl.node_weights, G, fwd_bounds=fb, fwd_status=fs,
+                                             stream=stream)
+
+        for _ in range(max(1, args.warmup)):
+            res = bstep()
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            bstep()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps, res[0] + res[1]
+
+    bms, gref = time_backward(prm)
+    out = {"workload": f"{name}: {WORKLOAD_TEXT[name]}", "n_elem": wl.n_elem,
+           "value": wl.n_elem / (bms * 1e-3), "unit": "elements/s", "ms_per_call": bms,
+           "forward_ms_per_step": ms_fwd, "forward_bounds_ms": b_fwd,
+           "vs_forward_step": bms / ms_fwd,
+           "what": "kbl_bounds_limit_backward given the forward bounds: limiter backward, "
+                   "bounds backward (envelopes and winners recomputed), gather; FP64; "
+                   "J = sum w rho_limited, w ~ N(0, 1)"}
+    print(f"[bench] {name} backward: {bms:.3f} ms/call (forward step {ms_fwd:.3f} ms)",
+          file=sys.stderr, flush=True)
+    if not args.no_mixed:
+        prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=kbl.PREC_MIXED_FP32)
+        mms, gmix = time_backward(prm_m)
+        scale = float(gref.abs().max())
+        diff = (gmix - gref).abs()
+        out["mixed_fp32"] = {
+            "ms_per_call": mms, "speedup_vs_fp64": bms / mms,
+            "max_err_rel_to_max_grad": float(diff.max()) / scale,
+            "p99_err_rel_to_max_grad": float(torch.quantile(diff.flatten()[:1 << 24].float(),
+                                                            0.99)) / scale,
+            "what": "gradient of the mixed forward (FP32 envelopes and winners, FP64 shares and "
+                    "chain rule), compared with the FP64 gradient"}
+        print(f"[bench] {name} mixed backward: {mms:.3f} ms/call, max err "
+              f"{float(diff.max()) / scale:.2e} of the max gradient", file=sys.stderr, flush=True)
+    return out
+
+
+def workload_config(name, wl):
+    sizes = wl.stencil_sizes()
+    cfg = {"workload": f"{name}: {WORKLOAD_TEXT.get(name, '')}", "n_elem": wl.n_elem,
+           "nodes_per_elem": wl.n_s, "velocity_grid": list(wl.grid.n[: wl.dim]),
+           "grid_mode": "stencil" if wl.grid.mode == 1 else "global",
+           "pairs_per_pass": wl.pairs()}
+    if sizes.min() != sizes.max():
+        h = np.bincount(sizes)
+        cfg["stencil_elements"] = {"min": int(sizes.min()), "max": int(sizes.max()),
+                                   "mean": float(sizes.mean()),
+                                   "histogram": {str(k): int(h[k]) for k in range(len(h)) if h[k]}}
+    else:
+        cfg["stencil_elements"] = int(sizes[0])
+    return cfg
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="quad256")
+    ap.add_argument("--workload", default="tri2m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
+    ap.add_argument("--no-second", action="store_true",
+                    help="skip the 1024^2-quad global-grid leg")
     ap.add_argument("--no-fr", action="store_true", help="skip the node-level stencil timing")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D velocity-grid timing")
-    ap.add_argument("--no-solver", action="store_true", help="skip the 1D FR solver step timing")
+    ap.add_argument("--solver", action="store_true", help="also time the 1D FR solver step")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the variant timings (energy reading, r = 0, independent "
                          "limiting, node-level stencils)")
@@ -421,33 +694,8 @@ def main(argv=None):
 
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
     dev = torch.device("cuda:0")
-    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
-    wl = synth.make_workload(args.workload)
-    g = wl.grid
-    st = torch.from_numpy(wl.states).to(dev)
-    rp = torch.from_numpy(wl.rowptr).to(dev)
-    cl = torch.from_numpy(wl.cols).to(dev)
-    tg = torch.from_numpy(wl.target).to(dev)
-    vg = kbl.make_vgrid(g.mode, g.n[: wl.dim], g.lo, g.hi, g.k)
-    prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
-    bounds = torch.empty((2 * (wl.dim + 2), wl.n_elem), dtype=torch.float64, device=dev)
-    bstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
-    lim = torch.empty_like(tg)
-    alpha = torch.empty((2, wl.n_elem), dtype=torch.float64, device=dev)
-    lstat = torch.empty(wl.n_elem, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream(dev)
-
-    def step(ev=None):
-        if ev is not None:
-            ev[0].record(stream)
-        kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm, out=bounds, status=bstat, stream=stream)
-        if ev is not None:
-            ev[1].record(stream)
-        kbl.limit(tg, bounds, wl.node_weights, wl.n_s, prm, out=lim, alpha=alpha, status=lstat,
-                  stream=stream)
-        if ev is not None:
-            ev[2].record(stream)
-
+    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
     if args.copy_calibration:
         n = args.copy_calibration * (1 << 20) // 8
         src = torch.ones(n, dtype=torch.float64, device=dev)
@@ -457,156 +705,49 @@ def main(argv=None):
         print(f"[bench] copy calibration: {n * 8} bytes read, {n * 8} bytes written",
               file=sys.stderr, flush=True)
         del src, dst
-    tuned = {}
 
-    def autotune(name, p):
-        # untimed: picks the tile and launch shape for this problem shape
-        if args.no_autotune:
-            return
-        c = kbl.autotune_bounds(st, rp, cl, wl.n_s, vg, p, sample_elems=65536, stream=stream)
-        tuned[name] = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
-        print(f"[bench] autotuned {name}: {tuned[name]}", file=sys.stderr, flush=True)
-
-    autotune("fp64", prm)
-    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        step(events[i])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_step = 1e3 * wall / args.steps
-    b_ms = float(np.mean([e[0].elapsed_time(e[1]) for e in events]))
-    l_ms = float(np.mean([e[1].elapsed_time(e[2]) for e in events]))
-    print(f"[bench] {ms_step:.3f} ms/step (bounds {b_ms:.3f} ms, limit {l_ms:.3f} ms)",
-          file=sys.stderr, flush=True)
-
-    pairs = wl.pairs()
-    ops = pairs * pair_ops(wl.dim)
-    achieved = ops / (b_ms * 1e-3)
-    n_cu = torch.cuda.get_device_properties(dev).multi_processor_count
-    kname, grid_threads = kernel_shape(kbl, wl.dim, tuned.get("fp64"), wl.n_elem, n_cu)
-    traffic, traffic_grid = (profiled_traffic(kname, grid_threads, args.workload, wl.dim)
-                             if grid_threads else (None, None))
-    roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-            "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": traffic,
-            "traffic_unit": "bytes per launch", "traffic_source": TRAFFIC_FILE,
-            "traffic_grid_threads": traffic_grid,
-            "kernel": kname, "grid_threads": grid_threads,
-            "ops_per_launch": ops, "pairs_per_launch": pairs,
-            "ops_per_pair": pair_ops(wl.dim), "kernel_ms": b_ms, "limit_ms": l_ms,
-            "limit_hbm_frac": (2 * wl.target.nbytes + bounds.numel() * 8 + alpha.numel() * 8
-                               + lstat.numel() * 4) / (l_ms * 1e-3) / HBM_PEAK}
-    out = {"metric": METRIC, "value": wl.n_elem / (ms_step * 1e-3), "unit": "elements/s",
-           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-           "data": "synthetic",
-           "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT.get(args.workload, '')}",
-                      "n_elem": wl.n_elem, "nodes_per_elem": wl.n_s,
-                      "velocity_grid": list(g.n[: wl.dim]), "precision": "fp64",
-                      "parity_tol": 1e-12},
-           "roofline": roof}
-    # the same step with the mixed-precision bounds (the limiter stays FP64)
+    print(f"[bench] generating {args.workload}", file=sys.stderr, flush=True)
+    wl = synth.make_workload(args.workload)
+    d = Dev(kbl, torch, wl, dev)
+    head = fp64_leg(args, kbl, torch, d, stream, n_cu, args.workload, args.steps)
+    cfg = workload_config(args.workload, wl)
+    cfg.update({"precision": "fp64", "parity_tol": 1e-12})
+    if head["launch"]:
+        cfg["launch"] = {"autotuned": head["launch"],
+                         "note": "workgroups_per_cu 0 = one workgroup per element"}
+    out = {"metric": METRIC, "value": head["value"], "unit": "elements/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic", "config": cfg,
+           "roofline": head["roofline"]}
     if wl.dim == 2 and not args.no_mixed:
-        mixed = {}
-        for name, prec in (("fp32_valu", kbl.PREC_MIXED_FP32), ("fp16_mfma", kbl.PREC_MIXED_FP16),
-                           ("bf16_mfma", kbl.PREC_MIXED_BF16)):
-            prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=prec)
-
-            def mstep(ev=None):
-                if ev is not None:
-                    ev[0].record(stream)
-                kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm_m, out=bounds, status=bstat,
-                                   stream=stream)
-                if ev is not None:
-                    ev[1].record(stream)
-                kbl.limit(tg, bounds, wl.node_weights, wl.n_s, prm, out=lim, alpha=alpha,
-                          status=lstat, stream=stream)
-                if ev is not None:
-                    ev[2].record(stream)
-
-            autotune(name, prm_m)
-            for _ in range(args.warmup):
-                mstep()
-            torch.cuda.synchronize()
-            mev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)]
-                   for _ in range(args.steps)]
-            t0 = time.perf_counter()
-            for i in range(args.steps):
-                mstep(mev[i])
-            torch.cuda.synchronize()
-            mwall = (time.perf_counter() - t0) / args.steps
-            mb = float(np.mean([e[0].elapsed_time(e[1]) for e in mev]))
-            mixed[name] = {"value": wl.n_elem / mwall, "unit": "elements/s",
-                           "ms_per_step": 1e3 * mwall, "bounds_ms": mb,
-                           "frac": ops / (mb * 1e-3) / VALU_PEAK_OPS,
-                           "speedup_vs_fp64": ms_step / (1e3 * mwall), "parity_tol": 1e-5}
-            print(f"[bench] mixed {name}: {1e3 * mwall:.3f} ms/step (bounds {mb:.3f} ms)",
-                  file=sys.stderr, flush=True)
-        out["mixed"] = mixed
-    if tuned:
-        out["config"]["launch"] = {"autotuned": tuned,
-                                   "note": "workgroups_per_cu 0 = one workgroup per element"}
-    # the hand-written backward of bounds + limiter, J = sum w rho_limited; the
-    # forward's bounds and status are handed over (as the autograd Function does)
-    if not args.no_backward and wl.dim <= 2:
-        G = torch.zeros_like(tg)
-        G[0] = torch.from_numpy(np.random.default_rng(7).standard_normal(wl.n_nodes)).to(dev)
-
-        def time_backward(p):
-            fb = torch.empty_like(bounds)
-            fs = torch.empty_like(bstat)
-            kbl.compute_bounds(st, rp, cl, wl.n_s, vg, p, out=fb, status=fs, stream=stream)
-
-            def bstep():
-                return kbl.bounds_limit_backward(st, rp, cl, wl.n_s, vg, p, tg, wl.node_weights,
-                                                 G, fwd_bounds=fb, fwd_status=fs, stream=stream)
-
-            for _ in range(max(1, args.warmup)):
-                res = bstep()
-            torch.cuda.synchronize()
-            bsteps = max(1, args.steps // 2)
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            for _ in range(bsteps):
-                bstep()
-            e1.record(stream)
-            torch.cuda.synchronize()
-            return e0.elapsed_time(e1) / bsteps, res[0] + res[1]
-
-        bms, gref = time_backward(prm)
-        out["backward"] = {"value": wl.n_elem / (bms * 1e-3), "unit": "elements/s",
-                           "ms_per_call": bms, "vs_forward_step": bms / ms_step,
-                           "what": "kbl_bounds_limit_backward given the forward bounds: limiter "
-                                   "backward, bounds backward (envelopes and winners recomputed), "
-                                   "gather; FP64; J = sum w rho_limited"}
-        print(f"[bench] backward: {bms:.3f} ms/call", file=sys.stderr, flush=True)
-        if wl.dim == 2 and not args.no_mixed:
-            prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=kbl.PREC_MIXED_FP32)
-            mms, gmix = time_backward(prm_m)
-            scale = float(gref.abs().max())
-            diff = (gmix - gref).abs()
-            out["backward"]["mixed_fp32"] = {
-                "ms_per_call": mms, "speedup_vs_fp64": bms / mms,
-                "max_err_rel_to_max_grad": float(diff.max()) / scale,
-                "p99_err_rel_to_max_grad": float(torch.quantile(diff.flatten()[:1 << 24].float(),
-                                                                0.99)) / scale,
-                "what": "gradient of the mixed forward (FP32 envelopes and winners, FP64 "
-                        "shares and chain rule), compared with the FP64 gradient"}
-            print(f"[bench] mixed backward: {mms:.3f} ms/call, max err "
-                  f"{float(diff.max()) / scale:.2e} of the max gradient", file=sys.stderr,
-                  flush=True)
+        out["mixed"] = mixed_legs(args, kbl, torch, d, stream, args.workload, args.steps,
+                                  head["ms_per_step"], head["bounds_ms"])
     if not args.no_variants and wl.dim == 2:
-        out["variants"] = time_variants(args, kbl, torch, synth, wl, st, rp, cl, tg, vg, stream,
-                                        ms_step, b_ms)
+        out["variants"] = time_variants(args, kbl, torch, synth, wl, d.st, d.rp, d.cl, d.tg,
+                                        d.vg, stream, head["ms_per_step"], head["bounds_ms"])
+    del d
+    torch.cuda.empty_cache()
+    second = "quad1024_sine"
+    if not args.no_second and args.workload != second:
+        print(f"[bench] generating {second}", file=sys.stderr, flush=True)
+        wl2 = synth.make_workload(second)
+        d2 = Dev(kbl, torch, wl2, dev)
+        steps2 = max(2, args.steps // 2)
+        leg = fp64_leg(args, kbl, torch, d2, stream, n_cu, second, steps2)
+        leg["config"] = workload_config(second, wl2)
+        if not args.no_mixed:
+            leg["mixed"] = mixed_legs(args, kbl, torch, d2, stream, second, steps2,
+                                      leg["ms_per_step"], leg["bounds_ms"])
+        out[second] = leg
+        del d2, wl2
+        torch.cuda.empty_cache()
+    if not args.no_backward and wl.dim == 2:
+        out["backward"] = backward_leg(args, kbl, torch, synth, stream)
+        torch.cuda.empty_cache()
     if not args.no_3d and wl.dim == 2:
         out["three_d"] = time_3d(args, kbl, torch, synth, stream)
-    if not args.no_solver and wl.dim == 2:
+    if args.solver and wl.dim == 2:
         out["fr1d_solver"] = time_fr1d(args, kbl, torch, stream)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)

@@ -232,7 +232,7 @@ def make_quad_workload(N: int = 256, p: int = 3, seed: int = BASE_SEED + 1,
 
 
 # ----------------------------------------------------------------------------
-# 2D jittered triangles (non-periodic square), vertex-neighbour stencils.
+# 2D jittered triangles (periodic square), vertex-neighbour stencils.
 # ----------------------------------------------------------------------------
 
 # Six-point interior rule on the reference triangle, degree 4, positive
@@ -288,28 +288,36 @@ def _vertex_stencil(tris: np.ndarray, n_vert: int):
 def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int = 64,
                       k: float = 4.0, gamma: float = 1.4, r_fac: float = 1e-3,
                       jitter: float = 0.2, outer=(1e-3, 1e-5), name: str = "tri") -> Workload:
+    """Periodic N x N lattice of jittered vertices, every cell split along a
+    seeded diagonal: 2 N^2 triangles, all of them with full vertex-neighbour
+    stencils (11 to 16 elements)."""
     rng = _rng(seed)
     h = 1.0 / N
-    iy, ix = np.divmod(np.arange((N + 1) * (N + 1)), N + 1)
-    vx = ix * h
-    vy = iy * h
-    interior_x = (ix > 0) & (ix < N)
-    interior_y = (iy > 0) & (iy < N)
-    vx = vx + np.where(interior_x, rng.uniform(-jitter, jitter, vx.size) * h, 0.0)
-    vy = vy + np.where(interior_y, rng.uniform(-jitter, jitter, vy.size) * h, 0.0)
+    jx = rng.uniform(-jitter, jitter, N * N) * h
+    jy = rng.uniform(-jitter, jitter, N * N) * h
     cy, cx = np.divmod(np.arange(N * N), N)
-    v00 = cy * (N + 1) + cx
-    v10 = v00 + 1
-    v01 = v00 + (N + 1)
-    v11 = v01 + 1
+
+    def corner(a, b):
+        # vertex id (wrapped) and its position unwrapped next to cell (cx, cy)
+        vid = ((cy + b) % N) * N + (cx + a) % N
+        return vid, (cx + a) * h + jx[vid], (cy + b) * h + jy[vid]
+
+    c00, c10, c01, c11 = corner(0, 0), corner(1, 0), corner(0, 1), corner(1, 1)
     diag = rng.integers(0, 2, N * N).astype(bool)
-    t1 = np.where(diag[:, None], np.stack([v00, v10, v11], 1), np.stack([v00, v10, v01], 1))
-    t2 = np.where(diag[:, None], np.stack([v00, v11, v01], 1), np.stack([v10, v11, v01], 1))
-    tris = np.stack([t1, t2], axis=1).reshape(2 * N * N, 3)
+
+    def pick(p, q):
+        return np.where(diag[:, None], p, q)
+
+    tri_of = lambda i: (np.stack([c00[i], c10[i], c11[i]], 1), np.stack([c00[i], c10[i], c01[i]], 1),
+                        np.stack([c00[i], c11[i], c01[i]], 1), np.stack([c10[i], c11[i], c01[i]], 1))
+    parts = [tri_of(i) for i in range(3)]          # ids, x, y: [N^2, 3] per triangle kind
+    t1 = [pick(P[0], P[1]) for P in parts]
+    t2 = [pick(P[2], P[3]) for P in parts]
+    tris, tx, ty = (np.stack([t1[i], t2[i]], axis=1).reshape(2 * N * N, 3) for i in range(3))
     n_tri = tris.shape[0]
     bary, wts = _tri_nodes()
-    X = bary @ vx[tris].T          # [6, n_tri]
-    Y = bary @ vy[tris].T
+    X = bary @ tx.T                # [6, n_tri]
+    Y = bary @ ty.T
     X = np.ascontiguousarray(X.T)  # [n_tri, 6]
     Y = np.ascontiguousarray(Y.T)
     r = np.hypot(X - 0.5, Y - 0.5)
@@ -321,7 +329,7 @@ def make_tri_workload(N: int = 1000, seed: int = BASE_SEED + 3, grid_nodes: int 
     ux = speed * (X - 0.5) / rs + 0.005 * _fourier(rng, X, Y)
     uy = speed * (Y - 0.5) / rs + 0.005 * _fourier(rng, X, Y)
     states = _to_conserved(gamma, rho, [ux, uy], pr)
-    rowptr, cols = _vertex_stencil(tris, vx.size)
+    rowptr, cols = _vertex_stencil(tris, N * N)
     grid = GridSpec(GRID_STENCIL, (grid_nodes, grid_nodes), (0.0, 0.0), (0.0, 0.0), k)
     target, jumpy = _limit_target(rng, states, rowptr, cols, 6, wts)
     return Workload(name, 2, gamma, n_tri, 6, states, target, rowptr, cols,

@@ -56,6 +56,18 @@ def test_pair_ops():
     assert bench.pair_ops(1) == 8
     assert bench.pair_ops(2) == 6
     assert bench.pair_ops(3) == 6
+    assert bench.MIXED_PAIR_OPS == 4
+
+
+def test_mfma_flops_count():
+    """64x64 grid, tile (2 x tiles, 4 k-steps, 2 waves): per element 4 x tiles,
+    4 envelopes, 4 k-steps, 3 (FP16) or 6 (BF16) 16x16x16 MFMAs."""
+    import types
+    from paper_2407_20966_amd import _lib
+    kbl = types.SimpleNamespace(_lib=_lib, PREC_MIXED_FP16=_lib.PREC_MIXED_FP16)
+    wl = types.SimpleNamespace(n_elem=10)
+    assert bench.mfma_flops_issued(wl, _lib.PREC_MIXED_FP16, 5, kbl) == 10 * 4 * 4 * 4 * 3 * 8192
+    assert bench.mfma_flops_issued(wl, _lib.PREC_MIXED_BF16, 5, kbl) == 10 * 4 * 4 * 4 * 6 * 8192
 
 
 def test_more_than_one_gpu_is_refused():
