@@ -48,14 +48,10 @@ constexpr int kTab = 64;            // states per B-table chunk
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kF16Scale = 16384.0f;            // 2^14, exact
 
-__device__ __forceinline__ short f2bf(float x) {   // round to nearest even
-    uint32_t u = __float_as_uint(x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (short)(u >> 16);
-}
-__device__ __forceinline__ float bf2f(short b) {
-    return __uint_as_float(((uint32_t)(uint16_t)b) << 16);
-}
+// FP32 -> BF16 (and FP16) by gfx950's conversion instructions, round to
+// nearest even; BF16 -> FP32 is exact.
+typedef __bf16 bf16v4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float bf_up(__bf16 b) { return (float)b; }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f32(float v) {
@@ -74,46 +70,78 @@ __device__ __forceinline__ float wave_max_f32(float v) {
                  fmaxf(__int_as_float(__builtin_amdgcn_readlane(b, 32)), __int_as_float(__builtin_amdgcn_readlane(b, 48))));
 }
 
+// The y factors (B operand) split once per element: FP16 hi/lo of the
+// factor scaled by 2^14, or BF16 in three parts.
+template <int KS, int CT>
+struct YSplit {
+    half4_t h[KS], l[KS];          // FP16
+    bf16x4_t b1[KS], b2[KS], b3[KS];   // BF16
+};
+template <int KS, int CT>
+__device__ __forceinline__ void split_y(const float* yb, YSplit<KS, CT>& y) {
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        if (CT == KBL_PREC_MIXED_FP16) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const float bv = yb[4 * k + i] * kF16Scale;
+                y.h[k][i] = (_Float16)bv;
+                y.l[k][i] = (_Float16)(bv - (float)y.h[k][i]);
+            }
+        } else {
+            bf16v4_t t1, t2, t3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float bv = yb[4 * k + i];
+                t1[i] = (__bf16)bv; bv -= bf_up(t1[i]);
+                t2[i] = (__bf16)bv; bv -= bf_up(t2[i]);
+                t3[i] = (__bf16)bv;
+            }
+            y.b1[k] = __builtin_bit_cast(bf16x4_t, t1);
+            y.b2[k] = __builtin_bit_cast(bf16x4_t, t2);
+            y.b3[k] = __builtin_bit_cast(bf16x4_t, t3);
+        }
+    }
+}
+
 // y-stage contraction of one envelope (one x tile) on MFMA: returns C
 // (lane l: factor l%16 at x rows 4(l/16) + i of the tile).
 template <int KS, int CT>
-__device__ __forceinline__ float4_t mfma_ystage(const float* f, const float* yb) {
+__device__ __forceinline__ float4_t mfma_ystage(const float* f, const YSplit<KS, CT>& y) {
     float4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         if (CT == KBL_PREC_MIXED_FP16) {
             // both operands are scaled by 2^14 (envelopes <= 1, factors < 2)
             // so that the low halves stay clear of FP16 subnormals
-            half4_t ah, al, bh, bl;
+            half4_t ah, al;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float av = f[4 * k + i] * kF16Scale, bv = yb[4 * k + i] * kF16Scale;
+                const float av = f[4 * k + i] * kF16Scale;
                 ah[i] = (_Float16)av;
                 al[i] = (_Float16)(av - (float)ah[i]);
-                bh[i] = (_Float16)bv;
-                bl[i] = (_Float16)(bv - (float)bh[i]);
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, bh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, bl, acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, y.h[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(al, y.h[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16f16(ah, y.l[k], acc, 0, 0, 0);
         } else {
-            bf16x4_t a1, a2, a3, b1, b2, b3;
+            bf16v4_t t1, t2, t3;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                float av = f[4 * k + i], bv = yb[4 * k + i];
-                a1[i] = f2bf(av); av -= bf2f(a1[i]);
-                a2[i] = f2bf(av); av -= bf2f(a2[i]);
-                a3[i] = f2bf(av);
-                b1[i] = f2bf(bv); bv -= bf2f(b1[i]);
-                b2[i] = f2bf(bv); bv -= bf2f(b2[i]);
-                b3[i] = f2bf(bv);
+                float av = f[4 * k + i];
+                t1[i] = (__bf16)av; av -= bf_up(t1[i]);
+                t2[i] = (__bf16)av; av -= bf_up(t2[i]);
+                t3[i] = (__bf16)av;
             }
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b1, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b2, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b1, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, b3, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, b2, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, b1, acc, 0, 0, 0);
+            const bf16x4_t a1 = __builtin_bit_cast(bf16x4_t, t1);
+            const bf16x4_t a2 = __builtin_bit_cast(bf16x4_t, t2);
+            const bf16x4_t a3 = __builtin_bit_cast(bf16x4_t, t3);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, y.b1[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, y.b2[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, y.b1[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a1, y.b3[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a2, y.b2[k], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a3, y.b1[k], acc, 0, 0, 0);
         }
     }
     return acc;
@@ -283,6 +311,17 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             }
         }
 
+        // The contraction starts from copies of the box, its spacing and the
+        // lane indices passed through an empty asm statement: otherwise the
+        // compiler forms the element-invariant node coordinates, weights and
+        // factors before the hot loop and keeps them live across it, which
+        // leaves one wave per SIMD.
+        double ebox[4] = {box[0], box[1], box[2], box[3]};
+        double ehx = hx, ehy = hy;
+        int ew = w, eg = g, exr = xr;
+        asm volatile("" : "+v"(ebox[0]), "+v"(ebox[1]), "+v"(ebox[2]), "+v"(ebox[3]), "+v"(ehx),
+                     "+v"(ehy), "+v"(ew), "+v"(eg), "+v"(exr));
+
         // MFMA paths: each envelope is exponentiated relative to its largest
         // value over the wave's nodes, rounded up to a power of two:
         // f = 2^(q log2 e - n) with n = ceil(max q log2 e), so the wave's
@@ -325,11 +364,11 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                 float H[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, HI[2] = {0, 0};
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
-                    const int ty = 16 * (j / 4) + 4 * g + (j % 4);
+                    const int ty = 16 * (j / 4) + 4 * eg + (j % 4);
                     float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f;
                     if (ty < p.ny) {
-                        const double u = node_pos(box[2], ty, hy);
-                        const double a0 = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
+                        const double u = node_pos(ebox[2], ty, ehy);
+                        const double a0 = ehy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
                         y0 = (float)a0;
                         y1 = (float)(u < 0.0 ? a0 * u : 0.0);
                         y2 = (float)(u < 0.0 ? 0.0 : a0 * u);
@@ -345,7 +384,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                     HI[1] = fmaf(__builtin_amdgcn_exp2f(iX[i][j] * kLog2e), y0, HI[1]);
                     __builtin_amdgcn_sched_barrier(0);
                 }
-                const XF X = x_factors(p, box, hx, 16 * (w + NW * i) + xr);
+                const XF X = x_factors(p, ebox, ehx, 16 * (ew + NW * i) + exr);
 #pragma unroll
                 for (int v = 0; v < 2; ++v) {
                     part[6 * v + 0] += X.w * H[v][0];
@@ -361,32 +400,34 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
         } else {
             // B operand: factor n = l%16 (0..3 used) at this lane's y nodes,
             // scaled by a power of two into [1, 2)
-            const double umax = fmax(fabs(box[2]), fabs(box[3]));
-            const double bound = xr == 0 ? hy : (xr == 3 ? hy * umax * umax : hy * umax);
-            const double yscale = (xr < 4 && bound > 0.0) ? ldexp(1.0, -ilogb(bound)) : 1.0;
+            const double umax = fmax(fabs(ebox[2]), fabs(ebox[3]));
+            const double bound = exr == 0 ? ehy : (exr == 3 ? ehy * umax * umax : ehy * umax);
+            const double yscale = (exr < 4 && bound > 0.0) ? ldexp(1.0, -ilogb(bound)) : 1.0;
             const double unscale =
                 (CT == KBL_PREC_MIXED_FP16 ? 1.0 / ((double)kF16Scale * kF16Scale) : 1.0) / yscale;
             float yb[TY];
 #pragma unroll
             for (int j = 0; j < TY; ++j) {
-                const int ty = 16 * (j / 4) + 4 * g + (j % 4);
+                const int ty = 16 * (j / 4) + 4 * eg + (j % 4);
                 double v = 0.0;
-                if (ty < p.ny && xr < 4) {
-                    const double u = node_pos(box[2], ty, hy);
-                    const double wy = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
-                    v = xr == 0 ? wy
-                      : xr == 1 ? (u < 0.0 ? wy * u : 0.0)
-                      : xr == 2 ? (u < 0.0 ? 0.0 : wy * u)
+                if (ty < p.ny && exr < 4) {
+                    const double u = node_pos(ebox[2], ty, ehy);
+                    const double wy = ehy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
+                    v = exr == 0 ? wy
+                      : exr == 1 ? (u < 0.0 ? wy * u : 0.0)
+                      : exr == 2 ? (u < 0.0 ? 0.0 : wy * u)
                                 : wy * u * u;
                 }
                 yb[j] = (float)(v * yscale);
             }
+            YSplit<KS, CT> ysp;
+            split_y<KS, CT>(yb, ysp);
 #pragma unroll
             for (int i = 0; i < TXW; ++i) {
                 // x rows of the C result held by this lane
                 XF X[4];
 #pragma unroll
-                for (int r = 0; r < 4; ++r) X[r] = x_factors(p, box, hx, 16 * (w + NW * i) + 4 * g + r);
+                for (int r = 0; r < 4; ++r) X[r] = x_factors(p, ebox, ehx, 16 * (ew + NW * i) + 4 * eg + r);
 #pragma unroll
                 for (int env = 0; env < 4; ++env) {
                     float f[TY];
@@ -395,25 +436,25 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                         const float q = env == 0 ? tn[i][j] : env == 1 ? tX[i][j] : env == 2 ? in_[i][j] : iX[i][j];
                         f[j] = __builtin_amdgcn_exp2f(fmaf(q, kLog2e, -nsh[env]));
                     }
-                    const float4_t c = mfma_ystage<KS, CT>(f, yb);
+                    const float4_t c = mfma_ystage<KS, CT>(f, ysp);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (xr < 4) {
+                    if (exr < 4) {
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const double h = c[r] * unscale;
                             if (env < 2) {
                                 double* pv = part + 6 * env;
-                                if (xr == 0) {
+                                if (exr == 0) {
                                     pv[0] += X[r].w * h; pv[1] += X[r].m * h; pv[2] += X[r].p * h;
                                     pv[5] += 0.5 * X[r].q * h;
-                                } else if (xr == 1) {
+                                } else if (exr == 1) {
                                     pv[3] += X[r].w * h;
-                                } else if (xr == 2) {
+                                } else if (exr == 2) {
                                     pv[4] += X[r].w * h;
                                 } else {
                                     pv[5] += 0.5 * X[r].w * h;
                                 }
-                            } else if (xr == 0) {
+                            } else if (exr == 0) {
                                 part[12 + env - 2] += X[r].w * h;
                             }
                         }
