@@ -65,6 +65,12 @@ static void nsum_add(nsum* a, double x) {
     a->s = t;
 }
 static double nsum_val(const nsum* a) { return a->s + a->c; }
+/* adds the product a b, including its rounding error (by fma) */
+static void nsum_add_prod(nsum* acc, double a, double b) {
+    const double p = a * b;
+    nsum_add(acc, p);
+    acc->c += fma(a, b, -p);
+}
 
 /* Ideal-gas pressure from conserved variables (Sec. 2.1). */
 static double pressure(int d, double gamma, const double* w) {
@@ -412,8 +418,10 @@ int oracle_limit(int d, double gamma, double p_floor, double eps,
  * returns dJ/dsolution (through the limiter) and dJ/dstates (through the
  * bounds of every element whose stencil holds the state).
  *
- * Conventions: min/max ties pick the first candidate (stencil order for the
- * envelopes, node order for extreme nodes, variable order for alpha_min);
+ * Conventions: ties of the envelopes go to the first state in stencil order
+ * for a maximum and to the last for a minimum; other min/max ties pick the
+ * first candidate (stencil order for the box ends, node order for extreme
+ * nodes, variable order for alpha_min);
  * alpha capped at 1 or set to 0 by the epsilon rule is locally constant; a
  * floored rho_min is constant; the indicator u_j < 0 of the momentum split
  * contributes nothing because its integrand vanishes at u_j = 0.  In
@@ -490,27 +498,32 @@ static void element_limit_backward(int d, double gamma, double p_floor, double e
         if (isnan(P)) P = -INFINITY;
         if (P < pmin) { pmin = P; jp = j; }
     }
+    /* the element sums below (adjoints of the mean, of alpha_P and of alpha)
+       can be small differences of large terms: they are compensated */
     double gwt[OR_MAXV * 64];      /* dJ/dw~ */
-    double gwbar[OR_MAXV] = {0, 0, 0, 0};
+    nsum gwbar[OR_MAXV];
+    for (int v = 0; v < OR_MAXV; ++v) gwbar[v].s = gwbar[v].c = 0.0;
     if (pmin < p_floor) {
         double pbar = pressure(d, gamma, wbar);
         if (pbar > p_floor) {
             double N = p_floor - pbar, D = pmin - pbar;
             double aP = fabs(N / D);
             double s = (N / D) >= 0 ? 1.0 : -1.0;
-            double gaP = 0.0;
+            nsum gaPs = {0.0, 0.0};
             for (int v = 0; v < nv; ++v)
                 for (int j = 0; j < n_s; ++j) {
                     gwt[v * n_s + j] = aP * G[v * n_s + j];
-                    gaP += G[v * n_s + j] * (wt[v * n_s + j] - wbar[v]);
-                    gwbar[v] += (1.0 - aP) * G[v * n_s + j];
+                    /* w~ - wbar = alpha (w - wbar) by eq. limiter */
+                    nsum_add_prod(&gaPs, G[v * n_s + j], amin * (w[v * n_s + j] - wbar[v]));
+                    nsum_add_prod(&gwbar[v], 1.0 - aP, G[v * n_s + j]);
                 }
+            const double gaP = nsum_val(&gaPs);
             /* aP = s N / D: d aP = s (dN / D - N dD / D^2), dN = -dPbar, dD = dPmin - dPbar */
             double gPbar = gaP * s * (-1.0 / D + N / (D * D));
             double gPmin = gaP * s * (-N / (D * D));
             double gp[OR_MAXV];
             pressure_grad(d, gamma, wbar, gp);
-            for (int v = 0; v < nv; ++v) gwbar[v] += gPbar * gp[v];
+            for (int v = 0; v < nv; ++v) nsum_add_prod(&gwbar[v], gPbar, gp[v]);
             double wn[OR_MAXV];
             for (int v = 0; v < nv; ++v) wn[v] = wt[v * n_s + jp];
             pressure_grad(d, gamma, wn, gp);
@@ -518,20 +531,21 @@ static void element_limit_backward(int d, double gamma, double p_floor, double e
         } else {
             /* alpha_P = 0: every node equals the mean */
             for (int v = 0; v < nv; ++v) {
-                for (int j = 0; j < n_s; ++j) { gwt[v * n_s + j] = 0.0; gwbar[v] += G[v * n_s + j]; }
+                for (int j = 0; j < n_s; ++j) { gwt[v * n_s + j] = 0.0; nsum_add(&gwbar[v], G[v * n_s + j]); }
             }
         }
     } else {
         for (int i = 0; i < nv * n_s; ++i) gwt[i] = G[i];
     }
     /* w~ = wbar + alpha (w - wbar) */
-    double galpha = 0.0;
+    nsum galphas = {0.0, 0.0};
     for (int v = 0; v < nv; ++v)
         for (int j = 0; j < n_s; ++j) {
             gw[v * n_s + j] += amin * gwt[v * n_s + j];
-            gwbar[v] += (1.0 - amin) * gwt[v * n_s + j];
-            galpha += gwt[v * n_s + j] * (w[v * n_s + j] - wbar[v]);
+            nsum_add_prod(&gwbar[v], 1.0 - amin, gwt[v * n_s + j]);
+            nsum_add_prod(&galphas, gwt[v * n_s + j], w[v * n_s + j] - wbar[v]);
         }
+    const double galpha = nsum_val(&galphas);
     if (vstar >= 0) {
         /* alpha = |(bnd - wbar) / dd|, dd = w[jstar] - wbar */
         const int v = vstar;
@@ -542,13 +556,13 @@ static void element_limit_backward(int d, double gamma, double p_floor, double e
         double gbnd = g / dstar;
         double gdd = -g * (bnd - wbar[v]) / (dstar * dstar);
         if (upper) gb[nv + v] += gbnd; else gb[v] += gbnd;
-        gwbar[v] += -gbnd;               /* from bnd - wbar */
+        nsum_add(&gwbar[v], -gbnd);      /* from bnd - wbar */
         gw[v * n_s + jstar] += gdd;      /* dd = w[jstar] - wbar */
-        gwbar[v] += -gdd;
+        nsum_add(&gwbar[v], -gdd);
     }
     /* wbar = sum c w / sum c */
     for (int v = 0; v < nv; ++v)
-        for (int j = 0; j < n_s; ++j) gw[v * n_s + j] += gwbar[v] * c[j] / csum;
+        for (int j = 0; j < n_s; ++j) gw[v * n_s + j] += nsum_val(&gwbar[v]) * c[j] / csum;
 }
 
 /*
@@ -611,14 +625,17 @@ static void element_bounds_backward(int d, double gamma, double r_fac, double rh
                 u[j] = lo[j] + t[j] * h[j];
                 M *= h[j] * ((t[j] == 0 || t[j] == n[j] - 1) ? 0.5 : 1.0);
             }
+            /* the subgradient of a min/max of tied states may take any of
+               them: a maximum goes to the first tied state in stencil order,
+               a minimum to the last */
             int win[4] = {0, 0, 0, 0};     /* Tmin, Tmax, Imin, Imax */
             double fv[4] = {INFINITY, -INFINITY, INFINITY, -INFINITY};
             for (int i = 0; i < S; ++i) {
                 double g = maxwellian(d, &st[i], u);
                 double gI = 0.5 * st[i].theta * delta * g;
-                if (g < fv[0]) { fv[0] = g; win[0] = i; }
+                if (g <= fv[0]) { fv[0] = g; win[0] = i; }
                 if (g > fv[1]) { fv[1] = g; win[1] = i; }
-                if (gI < fv[2]) { fv[2] = gI; win[2] = i; }
+                if (gI <= fv[2]) { fv[2] = gI; win[2] = i; }
                 if (gI > fv[3]) { fv[3] = gI; win[3] = i; }
             }
             double hu2 = 0.0;

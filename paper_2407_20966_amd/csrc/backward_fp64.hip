@@ -8,8 +8,16 @@
 //     per-stencil box mode the states that set each box end are located
 //     (first in stencil order on ties).
 //  2. The log-Maxwellian envelopes are recomputed together with their winning
-//     state per velocity node (strict comparisons: the first state wins ties).
-//     Nothing from the forward is stored.
+//     state per velocity node.  Nothing from the forward is stored.  In FP64
+//     each log value is shifted below -1 (by the element's log-peak plus one,
+//     folded into the per-state constant) and its lowest 8 mantissa bits are
+//     replaced by the state's index; one running min/max of these keys then
+//     yields the envelope's winner as well (a key differs from the log value
+//     by less than 2^-44 of it, so only states within that of each other can
+//     swap).  All keys being negative, among equal keys the maximum takes
+//     the first state in stencil order and the minimum the last.  The
+//     winner's log value is then recomputed exactly.  The mixed form tracks
+//     its FP32 winners with explicit comparisons (first state wins ties).
 //  3. Per node and envelope, the adjoint weight Phi of the moment rows
 //     (eq. rhobounds, Ebounds, mmbounds, mpbounds with the relaxation of
 //     eq. relaxed, the internal part of Sec. 3.6 and the trapezoid weights of
@@ -50,6 +58,16 @@ __device__ __forceinline__ void write_slots_zero(const BwdArgs& a, int64_t row0,
 }
 
 constexpr int kNoKey = 0x7fffffff;   // retired winner slot
+
+// Envelope keys: a negative log value with its lowest 8 mantissa bits
+// replaced by the state index s < 256.  One byte permute on the low dword:
+// bytes 3..1 from the value, byte 0 from s (selector bytes 4..7 pick the
+// first operand's bytes, 0..3 the second's).
+__device__ __forceinline__ double keyed(double v, int s) {
+    const uint32_t lo = __builtin_amdgcn_perm((uint32_t)__double2loint(v), (uint32_t)s, 0x07060500u);
+    return __hiloint2double(__double2hiint(v), (int)lo);
+}
+__device__ __forceinline__ int key_index(double k) { return __double2loint(k) & 0xff; }
 
 // Minimum waves per SIMD the register allocator targets.
 #ifndef KBL_BWD_WAVES
@@ -97,7 +115,7 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
 
         double box[4], ref[2];
         __syncthreads();
-        stencil_prologue<D, NT>(p, row0, S, red, sC, box, F32 ? ref : nullptr);
+        stencil_prologue<D, NT>(p, row0, S, red, sC, box, ref);
         const double cx = box[0] + 0.5 * (box[1] - box[0]);
         const double cy = D == 2 ? box[2] + 0.5 * (box[3] - box[2]) : 0.0;
         if (F32) {
@@ -162,15 +180,23 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
                 for (int j = 0; j < TY; ++j) {
                     q[0][i][j] = kInf; q[1][i][j] = -kInf; q[2][i][j] = kInf; q[3][i][j] = -kInf;
                 }
+            // shifts that put every log value at or below -1 (a <= log-peak);
+            // without internal degrees of freedom the internal envelopes get
+            // a finite stand-in far below any other value
+            const bool has_i = p.half_delta > 0.0;
+            const double kt = ref[0] + 1.0;
+            const double ki = has_i ? ref[1] + 1.0 : 0.0;
             for (int s = 0; s < (int)S; ++s) {
                 const Coef c = sC[s];
+                const double at = c.a - kt;
+                const double ai = has_i ? c.al - ki : -1e300;
                 double A[TX], AI[TX], B[TY];
 #pragma unroll
                 for (int i = 0; i < TX; ++i) {
                     const double d = ux[i] - c.ux;
                     const double t = c.nk * d;
-                    A[i] = fma(t, d, c.a);
-                    AI[i] = fma(t, d, c.al);
+                    A[i] = fma(t, d, at);
+                    AI[i] = fma(t, d, ai);
                 }
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
@@ -181,18 +207,19 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
                 for (int i = 0; i < TX; ++i)
 #pragma unroll
                     for (int j = 0; j < TY; ++j) {
-                        // strict comparisons: the first state keeps a tie
-                        const double qt = A[i] + B[j], qi = AI[i] + B[j];
-                        wn[0][i][j] = qt < q[0][i][j] ? s : wn[0][i][j];
-                        wn[1][i][j] = qt > q[1][i][j] ? s : wn[1][i][j];
-                        wn[2][i][j] = qi < q[2][i][j] ? s : wn[2][i][j];
-                        wn[3][i][j] = qi > q[3][i][j] ? s : wn[3][i][j];
+                        const double qt = keyed(A[i] + B[j], s), qi = keyed(AI[i] + B[j], s);
                         q[0][i][j] = fmin(q[0][i][j], qt);
                         q[1][i][j] = fmax(q[1][i][j], qt);
                         q[2][i][j] = fmin(q[2][i][j], qi);
                         q[3][i][j] = fmax(q[3][i][j], qi);
                     }
             }
+#pragma unroll
+            for (int env = 0; env < 4; ++env)
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) wn[env][i][j] = key_index(q[env][i][j]);
         } else {
             // winners from the FP32 envelopes; their FP64 log values are then
             // recomputed from the FP64 coefficients of the winning states
@@ -276,11 +303,13 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
                 double Jt = 0.0, dJdu[2] = {0.0, 0.0};
 #pragma unroll
                 for (int env = 0; env < 4; ++env) {
+                    // the winner's log value in FP64, as the forward forms it
                     const Coef& c = sC[wn[env][i][j]];
-                    double qv = F32 ? 0.0 : q[env][i][j];
-                    if (F32) {   // FP64 log value of the FP32 winner
-                        const double dx = u[0] - c.ux, dy = u[1] - c.uy;
-                        qv = fma(c.nk * dx, dx, env >= 2 ? c.al : c.a) + (c.nk * dy) * dy;
+                    const double dx = u[0] - c.ux;
+                    double qv = fma(c.nk * dx, dx, env >= 2 ? c.al : c.a);
+                    if (D == 2) {
+                        const double dy = u[1] - c.uy;
+                        qv += (c.nk * dy) * dy;
                     }
                     const double f = exp(qv);
                     const double wf = M * phi[env] * f;
@@ -395,11 +424,11 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
 
 // dJ/dstates[v][node] = sum over the distinct elements e of the stencil row of
 // the node's element J (stencils are symmetric: J's row lists every element
-// whose stencil holds J) of the slot of J's first entry in row e.  An element
-// listed twice in J's row (e.g. the left and right neighbour of a periodic
-// mesh two elements wide) is counted once; a repeated entry of J in row e
-// holds zero shares, since the first entry in stencil order wins every tie.
-// Fixed CSR order: deterministic.
+// whose stencil holds J) of the slots of every entry of J in row e.  An
+// element listed twice in J's row (e.g. the left and right neighbour of a
+// periodic mesh two elements wide) is counted once; when row e lists J
+// twice, the tied copies of J's states share its envelopes between their two
+// slots, so both are summed.  Fixed CSR order: deterministic.
 template <int D>
 __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* slot, double* gst) {
     constexpr int NV = D + 2;
@@ -424,7 +453,6 @@ __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* 
                     if (p.cols[k] == (int32_t)J) {
 #pragma unroll
                         for (int v = 0; v < NV; ++v) acc[v] += slot[(int64_t)v * nslot + k * p.n_s + jn];
-                        break;
                     }
                 }
             }

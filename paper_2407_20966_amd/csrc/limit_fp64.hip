@@ -43,6 +43,34 @@ __device__ __forceinline__ double grp_max(double v) {
     return v;
 }
 
+// Compensated sums for the backward, whose results can be small differences
+// of large terms: a value is carried as hi + lo, Knuth's TwoSum keeps the
+// rounding error of every addition and fma that of every product.
+struct Acc {
+    double hi = 0.0, lo = 0.0;
+    __device__ __forceinline__ void add(double x) {
+        const double s = hi + x, bb = s - hi;
+        lo += (hi - (s - bb)) + (x - bb);
+        hi = s;
+    }
+    __device__ __forceinline__ void add_prod(double a, double b) {
+        const double pr = a * b;
+        lo += fma(a, b, -pr);
+        add(pr);
+    }
+    __device__ __forceinline__ double value() const { return hi + lo; }
+};
+template <int G>
+__device__ __forceinline__ double grp_sum_c(Acc a) {
+#pragma unroll
+    for (int o = G / 2; o > 0; o >>= 1) {
+        const double h = __shfl_xor(a.hi, o, 64), l = __shfl_xor(a.lo, o, 64);
+        a.add(h);
+        a.lo += l;
+    }
+    return a.value();
+}
+
 template <int D>
 __device__ __forceinline__ double pressure(double gm1, const double* w) {
     double mm = w[1] * w[1];
@@ -223,29 +251,34 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
     const double pmin = grp_min<G>(P);
     const int jp = grp_first<G>(live && P == pmin, j);
 
-    double gwt[NV], gwbar[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) gwbar[v] = 0.0;
+    // Element sums (the adjoint of the mean, the alpha_P and alpha terms)
+    // are compensated: they can be small differences of large terms.
+    double gwt[NV];
+    Acc gwbar[NV];
     if (pmin < p.p_floor) {
         const double pbar = pressure<D>(p.gm1, wbar);
         if (pbar > p.p_floor) {
             const double N = p.p_floor - pbar, Dn = pmin - pbar;
             const double aP = fabs(N / Dn);
             const double sg = (N / Dn) >= 0.0 ? 1.0 : -1.0;
-            double gaP_l = 0.0;
+            Acc gaP_l;
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 gwt[v] = aP * Gw[v];
-                gaP_l += Gw[v] * (wt[v] - wbar[v]);
-                gwbar[v] += grp_sum<G>((1.0 - aP) * Gw[v]);
+                // w~ - wbar = alpha (w - wbar) (eq. limiter): formed from
+                // w - wbar, not by the cancelling difference w~ - wbar
+                gaP_l.add_prod(Gw[v], amin * (w[v] - wbar[v]));
+                Acc t;
+                t.add_prod(1.0 - aP, Gw[v]);
+                gwbar[v].add(grp_sum_c<G>(t));
             }
-            const double gaP = grp_sum<G>(gaP_l);
+            const double gaP = grp_sum_c<G>(gaP_l);
             const double gPbar = gaP * sg * (-1.0 / Dn + N / (Dn * Dn));
             const double gPmin = gaP * sg * (-N / (Dn * Dn));
             double gp[NV];
             pressure_grad<D>(p.gm1, wbar, gp);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) gwbar[v] += gPbar * gp[v];
+            for (int v = 0; v < NV; ++v) gwbar[v].add_prod(gPbar, gp[v]);
             if (j == jp) {
                 pressure_grad<D>(p.gm1, wt, gp);
 #pragma unroll
@@ -255,7 +288,9 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
                 gwt[v] = 0.0;
-                gwbar[v] += grp_sum<G>(Gw[v]);
+                Acc t;
+                t.add(Gw[v]);
+                gwbar[v].add(grp_sum_c<G>(t));
             }
         }
     } else {
@@ -263,14 +298,16 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
         for (int v = 0; v < NV; ++v) gwt[v] = Gw[v];
     }
     double gw[NV];
-    double ga_l = 0.0;
+    Acc ga_l;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         gw[v] = amin * gwt[v];
-        gwbar[v] += grp_sum<G>((1.0 - amin) * gwt[v]);
-        ga_l += gwt[v] * (w[v] - wbar[v]);
+        Acc t;
+        t.add_prod(1.0 - amin, gwt[v]);
+        gwbar[v].add(grp_sum_c<G>(t));
+        ga_l.add_prod(gwt[v], w[v] - wbar[v]);
     }
-    const double galpha = grp_sum<G>(ga_l);
+    const double galpha = grp_sum_c<G>(ga_l);
     double gb_term = 0.0;
     if (vstar >= 0) {
         double bnd = 0.0, wb = 0.0;          // register-array selects (no dynamic indexing)
@@ -283,7 +320,7 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
         const double gdd = -g * (bnd - wb) / (dstar * dstar);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
-            if (v == vstar) gwbar[v] += -gb_term - gdd;
+            if (v == vstar) { gwbar[v].add(-gb_term); gwbar[v].add(-gdd); }
         if (j == jstar) {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -291,7 +328,7 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
         }
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) gw[v] += gwbar[v] * c * p.inv_csum;
+    for (int v = 0; v < NV; ++v) gw[v] += gwbar[v].value() * c * p.inv_csum;
 
     if (bad_b) {
 #pragma unroll

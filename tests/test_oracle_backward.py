@@ -139,3 +139,28 @@ def test_duplicate_stencil_entries(N, seed):
     for a, b in ((gsol, gsol1), (gst, gst1), (gb, gb1)):
         np.testing.assert_allclose(a, b, rtol=0, atol=1e-14 * np.abs(b).max())
     fd_check(wl, "states", n_dofs=30, seed=N)
+
+
+@pytest.mark.parametrize("case", ["quad", "line"])
+def test_gradient_is_scale_invariant(case):
+    """J = sum G limited is homogeneous of degree one in (states, solution)
+    (moments linear in the Maxwellians, Sec. 3.3; eq. limiter and
+    eq. doublelimit commute with scaling away from the absolute floors), so
+    its gradient must not change when both are scaled.  A factor of the
+    wrong degree in the chain rule (e.g. a missing 1/rho in d ln g / d rho)
+    breaks this."""
+    if case == "quad":
+        wl = synth.make_quad_workload(N=3, seed=38, grid_nodes=20, name="sc_quad")
+        wl.target = wl.states + 10.0 * (wl.target - wl.states)
+    else:
+        wl = synth.make_line_workload(n_elem=6, seed=39, grid_nodes=64, name="sc_line")
+    G = np.random.default_rng(5).standard_normal(wl.target.shape)
+    ref = oracle.workload_backward(wl, G)
+    scale = max(np.abs(ref[1]).max(), np.abs(ref[0]).max())
+    assert scale > 0
+    for f in (3.0, 0.25):
+        got = oracle.backward(wl.dim, wl.gamma, f * wl.states, wl.rowptr, wl.cols, wl.n_s,
+                              wl.grid.mode, wl.grid.n[: wl.dim], wl.grid.lo, wl.grid.hi,
+                              wl.grid.k, wl.r_fac, f * wl.target, wl.node_weights, G)
+        for a, b in zip(got, ref):
+            np.testing.assert_allclose(a, b, rtol=0, atol=1e-10 * np.abs(b).max())
