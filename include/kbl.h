@@ -313,6 +313,40 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
                                      double* grad_bounds, uint32_t* elem_status,
                                      void* workspace, size_t workspace_bytes, void* stream);
 
+/* Size of the device array that kbl_bounds_limit_backward_noalloc uses as its
+ * workspace: 256 MiB per GPU. */
+#define KBL_NOALLOC_WORKSPACE_BYTES (256ull * 1024ull * 1024ull)
+
+/*
+ * kbl_bounds_limit_backward_noalloc - kbl_bounds_limit_backward for callers
+ * that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and errors as kbl_bounds_limit_backward, without the workspace: it uses a
+ * file-scope device array of KBL_NOALLOC_WORKSPACE_BYTES instead, one per
+ * GPU (its device address is looked up on the first call on each device;
+ * the array is held until the process ends).  Nothing is allocated: no
+ * hipMalloc, hipFree or allocating library call.
+ *   Returns KBL_ERR_WORKSPACE, before touching the device, when
+ *   kbl_backward_workspace_bytes() for these sizes exceeds
+ *   KBL_NOALLOC_WORKSPACE_BYTES (the quad mesh of 256 x 256 elements with
+ *   16 nodes and 5-element stencils needs about 172 MB).
+ * Every call on a GPU shares that GPU's array and leaves its contents there;
+ * every part of it that a call reads is written earlier in the same call, so
+ * nothing needs clearing.  Calls that overlap on one GPU (different streams
+ * or host threads) race on the array: serialise them.
+ */
+kbl_status kbl_bounds_limit_backward_noalloc(const kbl_params* params, int32_t dim,
+                                             int64_t n_elem, int32_t n_s, int64_t nnz,
+                                             const double* states, const int32_t* rowptr,
+                                             const int32_t* cols, const kbl_vgrid* vgrid,
+                                             const double* fwd_bounds,
+                                             const uint32_t* fwd_status,
+                                             const double* solution,
+                                             const double* node_weights,
+                                             const double* grad_limited, double* grad_states,
+                                             double* grad_solution, double* grad_bounds,
+                                             uint32_t* elem_status, void* stream);
+
 /*
  * kbl_status_summary - how many entries of a status array carry each bit:
  * counts[b] = number of i < n with bit b of elem_status[i] set, for b = 0..31.

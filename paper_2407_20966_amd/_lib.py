@@ -18,6 +18,7 @@ KBL_ERR_GRID = 3
 KBL_ERR_UNSUPPORTED = 4
 KBL_ERR_HIP = 5
 KBL_ERR_WORKSPACE = 6
+NOALLOC_WORKSPACE_BYTES = 256 << 20
 
 GRID_GLOBAL = 0
 GRID_STENCIL = 1
@@ -135,6 +136,11 @@ def _load():
                                                   C.POINTER(VGrid), P, P, P, P, P, P, P, P,
                                                   P, P, C.c_size_t, P]
         lib.kbl_bounds_limit_backward.restype = C.c_int
+        lib.kbl_bounds_limit_backward_noalloc.argtypes = [C.POINTER(Params), C.c_int32,
+                                                          C.c_int64, C.c_int32, C.c_int64, P, P,
+                                                          P, C.POINTER(VGrid), P, P, P, P, P, P,
+                                                          P, P, P, P]
+        lib.kbl_bounds_limit_backward_noalloc.restype = C.c_int
         lib.kbl_status_summary.argtypes = [P, C.c_int64, P, P]
         lib.kbl_status_summary.restype = C.c_int
         F = C.POINTER(Fr1dCfg)

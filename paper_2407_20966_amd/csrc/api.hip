@@ -202,6 +202,31 @@ kbl_status compute_bounds_impl(const kbl_params* params, int32_t dim, int64_t n_
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }
 
+// Workspace of kbl_bounds_limit_backward_noalloc: a file-scope device array
+// (each GPU the library runs on holds its own copy until the process ends).
+// In host code `scratch` only names the symbol; its device address comes
+// from hipGetSymbolAddress, once per device, and is kept per device.
+constexpr size_t kNoAllocWorkspaceBytes = (size_t)KBL_NOALLOC_WORKSPACE_BYTES;
+__device__ __align__(256) unsigned char scratch[kNoAllocWorkspaceBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on its first
+// use on that device).
+kbl_status scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return KBL_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return KBL_ERR_HIP;
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return KBL_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -408,15 +433,21 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
            align256(2 * nv * (size_t)n_elem * 8) + align256(nv * (size_t)nnz * (size_t)n_s * 8);
 }
 
-kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
-                                     int32_t n_s, int64_t nnz, const double* states,
-                                     const int32_t* rowptr, const int32_t* cols,
-                                     const kbl_vgrid* vgrid, const double* fwd_bounds,
-                                     const uint32_t* fwd_status, const double* solution,
-                                     const double* node_weights, const double* grad_limited,
-                                     double* grad_states, double* grad_solution,
-                                     double* grad_bounds, uint32_t* elem_status,
-                                     void* workspace, size_t workspace_bytes, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Shared body of the two backward entry points.  use_scratch: the workspace
+// is the file-scope `scratch` array of the current device (workspace and
+// workspace_bytes are ignored).
+kbl_status backward_impl(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
+                         int64_t nnz, const double* states, const int32_t* rowptr,
+                         const int32_t* cols, const kbl_vgrid* vgrid, const double* fwd_bounds,
+                         const uint32_t* fwd_status, const double* solution,
+                         const double* node_weights, const double* grad_limited,
+                         double* grad_states, double* grad_solution, double* grad_bounds,
+                         uint32_t* elem_status, void* workspace, size_t workspace_bytes,
+                         bool use_scratch, void* stream) {
     kbl::BoundsArgs fa;
     kbl_status rc = make_bounds_args(params, dim, n_elem, n_elem, n_s, nnz, states, rowptr, cols,
                                      vgrid, kMax1DBackwardNodes, &fa);
@@ -435,6 +466,12 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     if (!solution || !grad_limited || !grad_states || !grad_solution) return KBL_ERR_ARG;
     if (fwd_bounds && !fwd_status) return KBL_ERR_ARG;
     const size_t need = kbl_backward_workspace_bytes(dim, n_elem, n_s, nnz);
+    if (use_scratch) {
+        if (need > kNoAllocWorkspaceBytes) return KBL_ERR_WORKSPACE;
+        rc = scratch_address(&workspace);
+        if (rc != KBL_OK) return rc;
+        workspace_bytes = kNoAllocWorkspaceBytes;
+    }
     if (!workspace || workspace_bytes < need) return KBL_ERR_WORKSPACE;
     const size_t nv = (size_t)dim + 2;
     char* ws = (char*)workspace;
@@ -467,6 +504,41 @@ kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int6
     err = kbl::launch_bounds_bwd_fp64(fa, fs, gbnd, wslot, grad_states, elem_status, dim,
                                       prec != KBL_PREC_FP64, st);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+kbl_status kbl_bounds_limit_backward(const kbl_params* params, int32_t dim, int64_t n_elem,
+                                     int32_t n_s, int64_t nnz, const double* states,
+                                     const int32_t* rowptr, const int32_t* cols,
+                                     const kbl_vgrid* vgrid, const double* fwd_bounds,
+                                     const uint32_t* fwd_status, const double* solution,
+                                     const double* node_weights, const double* grad_limited,
+                                     double* grad_states, double* grad_solution,
+                                     double* grad_bounds, uint32_t* elem_status,
+                                     void* workspace, size_t workspace_bytes, void* stream) {
+    return backward_impl(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid, fwd_bounds,
+                         fwd_status, solution, node_weights, grad_limited, grad_states,
+                         grad_solution, grad_bounds, elem_status, workspace, workspace_bytes,
+                         false, stream);
+}
+
+kbl_status kbl_bounds_limit_backward_noalloc(const kbl_params* params, int32_t dim,
+                                             int64_t n_elem, int32_t n_s, int64_t nnz,
+                                             const double* states, const int32_t* rowptr,
+                                             const int32_t* cols, const kbl_vgrid* vgrid,
+                                             const double* fwd_bounds,
+                                             const uint32_t* fwd_status,
+                                             const double* solution,
+                                             const double* node_weights,
+                                             const double* grad_limited, double* grad_states,
+                                             double* grad_solution, double* grad_bounds,
+                                             uint32_t* elem_status, void* stream) {
+    return backward_impl(params, dim, n_elem, n_s, nnz, states, rowptr, cols, vgrid, fwd_bounds,
+                         fwd_status, solution, node_weights, grad_limited, grad_states,
+                         grad_solution, grad_bounds, elem_status, nullptr, 0, true, stream);
 }
 
 kbl_status kbl_status_summary(const uint32_t* elem_status, int64_t n, uint64_t* counts,
