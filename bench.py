@@ -551,8 +551,11 @@ def mixed_legs(args, kbl, torch, d, stream, label, steps, ms_fp64, b_fp64):
     wl = d.wl
     prm = kbl.make_params(wl.gamma, r_fac=wl.r_fac)
     out = {}
-    for name, prec in (("fp32_valu", kbl.PREC_MIXED_FP32), ("fp16_mfma", kbl.PREC_MIXED_FP16),
-                       ("bf16_mfma", kbl.PREC_MIXED_BF16)):
+    forms = (("fp32_valu", kbl.PREC_MIXED_FP32), ("fp16_mfma", kbl.PREC_MIXED_FP16),
+             ("bf16_mfma", kbl.PREC_MIXED_BF16))
+    for name, prec in forms:
+        if name not in args.mixed_forms.split(","):
+            continue
         prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=prec)
         tuned = autotune(args, kbl, d, prm_m, stream, f"{label} {name}")
         ms, b_ms, l_ms = time_step(kbl, torch, d, prm_m, prm, stream, steps, args.warmup)
@@ -669,6 +672,8 @@ def main(argv=None):
     ap.add_argument("--workload", default="tri2m")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision timings")
+    ap.add_argument("--mixed-forms", default="fp32_valu,fp16_mfma,bf16_mfma",
+                    help="comma-separated mixed forms to time (profiling runs)")
     ap.add_argument("--no-backward", action="store_true", help="skip the backward timing")
     ap.add_argument("--no-second", action="store_true",
                     help="skip the 1024^2-quad global-grid leg")
