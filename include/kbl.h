@@ -268,12 +268,16 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
  * given G = dJ/dlimited: the derivatives of eq. fminmax, relaxed, rhobounds,
  * Ebounds, mmbounds, mpbounds, truncdomain (Sec. 3.3-3.7), the density floor
  * and eq. alpha, limiter, pmin, doublelimit (Sec. 3.4, 3.8).  The min/max
- * distributions are recomputed, never stored; the min/max envelopes take
- * their subgradient at the first winning state in stencil order, the limiter
- * at its active term (first node and variable on ties); alpha capped at 1,
- * alpha set to 0 by the epsilon rule, alpha_P = 0 and a floored rho_min are
- * constants.  In KBL_GRID_STENCIL mode the velocity box moves with its
- * extreme states and that dependence is differentiated too.
+ * distributions are recomputed, never stored; at a tie the max envelopes
+ * take their subgradient at the first winning state in stencil order and
+ * the min envelopes at the last, the limiter at its active term (first node
+ * and variable on ties); alpha capped at 1, alpha set to 0 by the epsilon
+ * rule, alpha_P = 0 and a floored rho_min are constants.  In
+ * KBL_GRID_STENCIL mode the velocity box moves with its extreme states and
+ * that dependence is differentiated too.  The bounds' adjoint is linear in
+ * dJ/dbounds, which is zero for every element whose limiter binds no bound:
+ * such elements contribute exactly zero and their distributions are not
+ * recomputed, so the cost grows with the number of limited elements.
  *
  * params->precision selects the forward being differentiated:
  *   KBL_PREC_FP64   everything in FP64;

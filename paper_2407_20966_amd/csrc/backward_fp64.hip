@@ -111,6 +111,19 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
 #pragma unroll
         for (int v = 0; v < 2 * (D + 2); ++v) gb[v] = a.gbnd[(int64_t)v * p.n_elem + e];
         if (fst & KBL_ST_RHO_FLOOR) gb[0] = 0.0;   // the floored rho_min is constant
+        // Every term below is linear in dJ/dbounds, which the limiter's
+        // adjoint leaves at zero unless a bound binds (alpha < 1 set by eq.
+        // alpha): such elements contribute exactly zero and are skipped.
+        // Bit test: +-0 only (a NaN or infinite adjoint is propagated).
+        bool active = false;
+#pragma unroll
+        for (int v = 0; v < 2 * (D + 2); ++v)
+            active |= ((uint64_t)__double_as_longlong(gb[v]) << 1) != 0;
+        if (!active) {
+            write_slots_zero<D, NT>(a, row0, S);
+            if (a.status && tid == 0) a.status[e] = fst;
+            continue;
+        }
         constexpr int NV = D + 2;
 
         double box[4], ref[2];

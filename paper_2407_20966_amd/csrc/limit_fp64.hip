@@ -153,36 +153,53 @@ __global__ __launch_bounds__(kThreads) void limit_fp64(LimitArgs p) {
         bad_b |= !isfinite(b[v]);
     }
 
+    // alpha_v = min(1, |b_max - wbar| / |w_max - wbar|, |b_min - wbar| /
+    // |w_min - wbar|) (eq. alpha).  The ratios are ordered by cross products
+    // of their (non-negative) numerators and denominators, which are bounded
+    // below by eps, and only the smallest is divided: one division per
+    // element for the coupled minimum, one per component when independent.
     uint32_t st = 0;
-    double wbar[NV], acomp[NV];
-    double amin = 1.0;
+    double wbar[NV], rn[NV], rd[NV];
+    bool eps0 = false;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         wbar[v] = grp_sum<G>(c * w[v]) * p.inv_csum;
         const double wmax = grp_max<G>(live ? w[v] : -kInf);
         const double wmin = grp_min<G>(live ? w[v] : kInf);
         if (wbar[v] < b[v] || wbar[v] > b[NV + v]) st |= KBL_ST_MEAN_OUTSIDE;
-        const double dp = wmax - wbar[v], dm = wmin - wbar[v];
-        double av;
-        if (fabs(dm) < p.eps || fabs(dp) < p.eps) {
-            av = 0.0;
-            st |= KBL_ST_EPS_RULE;
-        } else {
-            av = 1.0;
-            const double ru = fabs((b[NV + v] - wbar[v]) / dp);
-            const double rl = fabs((b[v] - wbar[v]) / dm);
-            if (ru < av) av = ru;
-            if (rl < av) av = rl;
+        const double du = fabs(wmax - wbar[v]), dl = fabs(wmin - wbar[v]);
+        const double nu = fabs(b[NV + v] - wbar[v]), nl = fabs(b[v] - wbar[v]);
+        const bool lo = nl * du < nu * dl;          // the lower side binds first
+        const bool ev = dl < p.eps || du < p.eps;
+        eps0 |= ev;
+        rn[v] = ev ? 0.0 : (lo ? nl : nu);          // ratio 0 under the eps rule
+        rd[v] = ev ? 1.0 : (lo ? dl : du);
+    }
+    if (eps0) st |= KBL_ST_EPS_RULE;
+    double acomp[NV];
+    double amin;
+    if (!p.independent) {
+        double Nm = 1.0, Dm = 1.0;                  // smallest ratio, as Nm / Dm
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+            if (rn[v] * Dm < Nm * rd[v]) { Nm = rn[v]; Dm = rd[v]; }
+        amin = Nm < Dm ? Nm / Dm : 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acomp[v] = amin;
+    } else {
+        amin = 1.0;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            acomp[v] = rn[v] < rd[v] ? rn[v] / rd[v] : 1.0;
+            amin = fmin(amin, acomp[v]);
         }
-        acomp[v] = av;
-        if (av < amin) amin = av;
     }
     if (amin < 1.0) st |= KBL_ST_LIMITED;
 
     // coupled (eq. limiter) or independent per-component blend
     double wt[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + (p.independent ? acomp[v] : amin) * (w[v] - wbar[v]);
+    for (int v = 0; v < NV; ++v) wt[v] = wbar[v] + acomp[v] * (w[v] - wbar[v]);
 
     double P = live ? pressure<D>(p.gm1, wt) : kInf;
     if (isnan(P)) P = -kInf;

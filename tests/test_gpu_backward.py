@@ -136,6 +136,20 @@ def test_quad_stencil_box(kbl, n):
     compare_with_oracle(kbl, wl)
 
 
+def test_quad_few_limited(kbl):
+    """The unamplified target: most elements bind no bound, their bounds'
+    adjoint is zero and the kernel skips them; the gradient must still match
+    the oracle's dense evaluation everywhere."""
+    wl = synth.make_quad_workload(N=8, seed=48, grid_nodes=24, name="b_quad_sparse")
+    st, tg, rp, cl, vg, prm = dev_inputs(kbl, wl)
+    b, _ = kbl.compute_bounds(st, rp, cl, wl.n_s, vg, prm)
+    _, alpha, _ = kbl.limit(tg, b, wl.node_weights, wl.n_s, prm)
+    n_lim = int((alpha[0] < 1).sum().item())
+    print(f"[bwd] b_quad_sparse: {n_lim}/{wl.n_elem} elements limited", flush=True)
+    assert 0 < n_lim < wl.n_elem // 2
+    compare_with_oracle(kbl, wl)
+
+
 def test_quad_global_box(kbl):
     wl = synth.make_quad_workload(N=4, seed=44, field_kind="sine", grid_nodes=32,
                                   grid_mode=GRID_GLOBAL, name="b_quad_gl")
