@@ -124,6 +124,90 @@ def profiled_traffic(kernel: str, grid_threads: int, workload: str, dim: int):
     return other
 
 
+def _counter_per_dispatch(csv_path: str, counter: str):
+    """{dispatch id: (kernel name, grid size, value)} of one counter from a
+    rocprofv3 counter-collection CSV (rows of one dispatch summed)."""
+    import csv
+    out = {}
+    with open(csv_path) as fh:
+        for r in csv.DictReader(fh):
+            if r["Counter_Name"] != counter:
+                continue
+            k = r["Dispatch_Id"]
+            name, grid, v = out.get(k, (r["Kernel_Name"], int(r["Grid_Size"]), 0.0))
+            out[k] = (name, grid, v + float(r["Counter_Value"]))
+    return dict(sorted(out.items(), key=lambda kv: int(kv[0])))
+
+
+def write_traffic(workload: str, fetch_csv: str, write_csv: str) -> dict:
+    """Turns a FETCH_SIZE run and a WRITE_SIZE run of bench.py (each with
+    --copy-calibration) into an entry of the traffic file, replacing an entry
+    of the same workload, kernel and grid.  Calibration: the device copy reads
+    as many bytes as it writes, and WRITE_SIZE counts the bytes written, so
+    FETCH_SIZE is scaled by WRITE/FETCH of the copy.  The profiled launch is
+    the kernel and grid of the last FP64 bounds dispatch (the timed launches;
+    the autotuner's candidates run before them)."""
+    import synth
+    fetch = _counter_per_dispatch(fetch_csv, "FETCH_SIZE")
+    write = _counter_per_dispatch(write_csv, "WRITE_SIZE")
+
+    def copy_kib(d):
+        v = [x[2] for x in d.values() if "copyBuffer" in x[0]]
+        if not v:
+            raise SystemExit("no calibration copy in the counter runs (use --copy-calibration)")
+        return v[-1]
+
+    scale = copy_kib(write) / copy_kib(fetch)
+
+    def bounds_launches(d):
+        runs, last = {}, None
+        for name, grid, v in d.values():               # in dispatch order
+            if "bounds_fp64_" in name and "bwd" not in name:
+                kname = name.replace("void kbl::(anonymous namespace)::", "").split("(kbl")[0]
+                runs.setdefault((kname, grid), []).append(v)
+                last = (kname, grid)
+        # the timed launches come last (after the autotuner's candidates)
+        return last, runs[last]
+
+    (kname, grid), fv = bounds_launches(fetch)
+    (kname_w, grid_w), wv = bounds_launches(write)
+    if (kname, grid) != (kname_w, grid_w):
+        raise SystemExit(f"the two runs profiled different launches: {kname} {grid} / "
+                         f"{kname_w} {grid_w}")
+    f_kib, w_kib = sum(fv) / len(fv), sum(wv) / len(wv)
+    wl = synth.make_workload(workload)
+    nv = wl.dim + 2
+    alg = (wl.n_nodes * nv * 8 + (wl.n_elem + 1) * 4 + wl.nnz * 4 + 2 * nv * wl.n_elem * 8
+           + wl.n_elem * 4)
+    nbytes = (f_kib * scale + w_kib) * 1024.0
+    entry = {"workload": workload, "kernel": kname, "grid_threads": str(grid),
+             "source_sha256": kernel_sources_sha(wl.dim),
+             "fetch_kib_per_dispatch": f"{f_kib:.1f}", "write_kib_per_dispatch": f"{w_kib:.1f}",
+             "fetch_scale": f"{scale:.4f}", "bytes_per_launch": f"{nbytes:.0f}",
+             "algorithmic_bytes_per_launch": str(alg)}
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    head, blocks = [], []
+    for line in open(path):
+        if line.strip() == "[entry]":
+            blocks.append([])
+        (blocks[-1] if blocks else head).append(line)
+    keep = []
+    for b in blocks:
+        kv = dict(l.strip().split(" = ", 1) for l in b if " = " in l)
+        if (kv.get("workload"), kv.get("kernel"), kv.get("grid_threads")) != \
+                (workload, kname, str(grid)):
+            keep.append(b)
+    with open(path, "w") as fh:
+        fh.writelines(head)
+        for b in keep:
+            fh.writelines(b)
+        fh.write("[entry]\n")
+        for k, v in entry.items():
+            fh.write(f"{k} = {v}\n")
+        fh.write(f"# ratio {nbytes / alg:.3f}\n")
+    return entry
+
+
 def pair_ops(dim: int) -> int:
     """Algorithmic VALU lane-ops per (stencil state, velocity node) pair, FP64.
 
@@ -711,7 +795,14 @@ def main(argv=None):
                     help="use the default launch configuration instead of an autotuned one")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="also run one plain device copy of MIB MiB (counter calibration)")
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="no timing: turn the counter CSVs of a FETCH_SIZE and a WRITE_SIZE "
+                         "run on --workload into its entry of " + TRAFFIC_FILE)
     args = ap.parse_args(argv)
+    if args.write_traffic:
+        e = write_traffic(args.workload, *args.write_traffic)
+        print(json.dumps(e))
+        return 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: the bounds path runs on a single MI355X "
               "(there is no multi-GPU path); use --gpus 1", file=sys.stderr)

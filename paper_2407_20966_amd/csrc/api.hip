@@ -430,7 +430,8 @@ size_t kbl_backward_workspace_bytes(int32_t dim, int64_t n_elem, int32_t n_s, in
     if ((dim != 1 && dim != 2) || n_elem < 0 || n_s < 1 || nnz < 0) return 0;
     const size_t nv = (size_t)dim + 2;
     return align256(2 * nv * (size_t)n_elem * 8) + align256((size_t)n_elem * 4) +
-           align256(2 * nv * (size_t)n_elem * 8) + align256(nv * (size_t)nnz * (size_t)n_s * 8);
+           align256(2 * nv * (size_t)n_elem * 8) + align256(nv * (size_t)nnz * (size_t)n_s * 8) +
+           align256(4) + align256((size_t)n_elem * 4) + align256((size_t)n_elem);
 }
 
 }  // extern "C"
@@ -478,7 +479,11 @@ kbl_status backward_impl(const kbl_params* params, int32_t dim, int64_t n_elem, 
     double* wb = (double*)ws;                          ws += align256(2 * nv * (size_t)n_elem * 8);
     uint32_t* wst = (uint32_t*)ws;                     ws += align256((size_t)n_elem * 4);
     double* wgb = (double*)ws;                         ws += align256(2 * nv * (size_t)n_elem * 8);
-    double* wslot = (double*)ws;
+    double* wslot = (double*)ws;                       ws += align256(nv * (size_t)nnz * (size_t)n_s * 8);
+    kbl::ActiveSet act;
+    act.count = (uint32_t*)ws;                         ws += align256(4);
+    act.list = (int32_t*)ws;                           ws += align256((size_t)n_elem * 4);
+    act.flag = (uint8_t*)ws;
     double* gbnd = grad_bounds ? grad_bounds : wgb;
     hipStream_t st = (hipStream_t)stream;
     hipError_t err;
@@ -499,9 +504,9 @@ kbl_status backward_impl(const kbl_params* params, int32_t dim, int64_t n_elem, 
     }
     la.solution = solution;
     la.bounds = fb;
-    err = kbl::launch_limit_bwd_fp64(la, dim, grad_limited, grad_solution, gbnd, st);
+    err = kbl::launch_limit_bwd_fp64(la, dim, grad_limited, grad_solution, gbnd, act, st);
     if (err != hipSuccess) return KBL_ERR_HIP;
-    err = kbl::launch_bounds_bwd_fp64(fa, fs, gbnd, wslot, grad_states, elem_status, dim,
+    err = kbl::launch_bounds_bwd_fp64(fa, fs, gbnd, act, wslot, grad_states, elem_status, dim,
                                       prec != KBL_PREC_FP64, st);
     return err == hipSuccess ? KBL_OK : KBL_ERR_HIP;
 }

@@ -1,9 +1,13 @@
 // FP64 backward of the kinetic bounds (the differentiable form), gfx950.
 //
 // Given dJ/db per element (from the limiter backward), this computes dJ/d(state)
-// for every stencil state of every element, then gathers them per node.
+// for every stencil state of every element, then gathers them per node.  The
+// adjoint is linear in dJ/db, which is zero wherever no bound binds the
+// limiter (alpha = 1 or set by the epsilon rule, eq. alpha): only the
+// elements the limiter's adjoint listed are visited, and the gather skips
+// the others.
 //
-// Per element (one workgroup, the FP64 forward's tiling):
+// Per listed element (one workgroup, the FP64 forward's tiling):
 //  1. Prologue as in the forward (coefficients in LDS, velocity box); in
 //     per-stencil box mode the states that set each box end are located
 //     (first in stencil order on ties).
@@ -34,8 +38,8 @@
 //     the extreme states (lo = U - k sqrt(theta), hi = U + k sqrt(theta)).
 //  5. (rho, U, theta) adjoints are mapped to conserved variables and written
 //     to this element's stencil slots.
-// A gather kernel then sums, for each node, the slots that refer to it,
-// walking the (symmetric) stencil in CSR order.
+// A gather kernel then sums, for each node, the slots of listed elements that
+// refer to it, walking the (symmetric) stencil in CSR order.
 #include "bounds_common.h"
 
 namespace kbl {
@@ -45,8 +49,10 @@ struct BwdArgs {
     BoundsArgs f;              // forward geometry and parameters
     const uint32_t* fstatus;   // forward status per element
     const double* gbnd;        // [2nv][n_elem] dJ/dbounds
-    double* slot;              // [nv][nnz * n_s] per-slot state gradients (out)
-    uint32_t* status;          // backward status per element (or null)
+    const uint32_t* act_count; // number of listed elements
+    const int32_t* act_list;   // elements whose bounds' adjoint is nonzero
+    double* slot;              // [nv][nnz * n_s] per-slot state gradients (out; listed
+                               // elements' slots only)
 };
 
 template <int D, int NT>
@@ -93,27 +99,25 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     const int64_t nslot = p.nnz * p.n_s;
 
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
-        const int64_t e = er.e;
+    // only the listed elements: every other element's bounds' adjoint is
+    // zero, and so is its contribution (the gather skips its slots)
+    const uint32_t n_act = *a.act_count;
+    for (uint32_t ia = blockIdx.x; ia < n_act; ia += gridDim.x) {
+        const int64_t e = a.act_list[ia];
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
-        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {          // no addressable slots
-            if (a.status && tid == 0) a.status[e] = KBL_ST_BAD_STENCIL;
-            continue;
-        }
+        if (row0 < 0 || row1 <= row0 || row1 > p.nnz) continue;  // no addressable slots
         const int64_t S = (row1 - row0) * p.n_s;
         const uint32_t fst = a.fstatus[e];
         if (S > kMaxStates || (fst & (KBL_ST_BAD_STENCIL | KBL_ST_INADMISSIBLE))) {
             write_slots_zero<D, NT>(a, row0, S);
-            if (a.status && tid == 0) a.status[e] = fst | (S > kMaxStates ? KBL_ST_TOO_LARGE : 0u);
             continue;
         }
         double gb[2 * (D + 2)];
 #pragma unroll
         for (int v = 0; v < 2 * (D + 2); ++v) gb[v] = a.gbnd[(int64_t)v * p.n_elem + e];
         if (fst & KBL_ST_RHO_FLOOR) gb[0] = 0.0;   // the floored rho_min is constant
-        // Every term below is linear in dJ/dbounds, which the limiter's
-        // adjoint leaves at zero unless a bound binds (alpha < 1 set by eq.
-        // alpha): such elements contribute exactly zero and are skipped.
+        // Every term below is linear in dJ/dbounds; a listed element whose
+        // only nonzero entry was the floored rho_min contributes zero.
         // Bit test: +-0 only (a NaN or infinite adjoint is propagated).
         bool active = false;
 #pragma unroll
@@ -121,7 +125,6 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
             active |= ((uint64_t)__double_as_longlong(gb[v]) << 1) != 0;
         if (!active) {
             write_slots_zero<D, NT>(a, row0, S);
-            if (a.status && tid == 0) a.status[e] = fst;
             continue;
         }
         constexpr int NV = D + 2;
@@ -431,7 +434,6 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
             a.slot[at] = out_rho;
             a.slot[(int64_t)(D + 1) * nslot + at] = g_th * p.gm1 / st.rho;
         }
-        if (a.status && tid == 0) a.status[e] = fst;
     }
 }
 
@@ -443,7 +445,8 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
 // twice, the tied copies of J's states share its envelopes between their two
 // slots, so both are summed.  Fixed CSR order: deterministic.
 template <int D>
-__global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* slot, double* gst) {
+__global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* slot,
+                                                    const uint8_t* act_flag, double* gst) {
     constexpr int NV = D + 2;
     const int64_t nslot = p.nnz * p.n_s;
     for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < p.n_nodes;
@@ -456,7 +459,7 @@ __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* 
         if (r0 >= 0 && r1 > r0 && r1 <= p.nnz) {
             for (int64_t r = r0; r < r1; ++r) {
                 const int32_t e = p.cols[r];
-                if (e < 0 || e >= p.n_elem) continue;
+                if (e < 0 || e >= p.n_elem || !act_flag[e]) continue;   // unlisted: zero
                 bool seen = false;
                 for (int64_t q = r0; q < r && !seen; ++q) seen = p.cols[q] == e;
                 if (seen) continue;
@@ -475,13 +478,22 @@ __global__ __launch_bounds__(256) void gather_slots(BoundsArgs p, const double* 
     }
 }
 
-// Flags elements whose stencil lists an element J whose own row does not list
-// them back (the gather would miss that slot).
-__global__ __launch_bounds__(256) void check_symmetric(BoundsArgs p, uint32_t* status) {
+// Backward status per element: the forward's status, KBL_ST_BAD_STENCIL alone
+// for a row outside the stencil arrays, KBL_ST_TOO_LARGE beyond kMaxStates
+// states (zero gradient), and KBL_ST_ASYMMETRIC when the stencil lists an
+// element J whose own row does not list it back (the gather would miss
+// that slot).
+__global__ __launch_bounds__(256) void bwd_status(BoundsArgs p, const uint32_t* fstatus,
+                                                  uint32_t* status) {
     for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < p.n_elem;
          e += (int64_t)gridDim.x * 256) {
         const int64_t r0 = p.rowptr[e], r1 = p.rowptr[e + 1];
-        if (r0 < 0 || r1 <= r0 || r1 > p.nnz) continue;
+        if (r0 < 0 || r1 <= r0 || r1 > p.nnz) {
+            status[e] = KBL_ST_BAD_STENCIL;
+            continue;
+        }
+        uint32_t st = fstatus[e];
+        if ((r1 - r0) * p.n_s > kMaxStates) st |= KBL_ST_TOO_LARGE;
         bool ok = true;
         for (int64_t r = r0; r < r1 && ok; ++r) {
             const int32_t J = p.cols[r];
@@ -493,13 +505,16 @@ __global__ __launch_bounds__(256) void check_symmetric(BoundsArgs p, uint32_t* s
                     if (p.cols[k] == (int32_t)e) { found = true; break; }
             ok = found;
         }
-        if (!ok) status[e] |= KBL_ST_ASYMMETRIC;
+        status[e] = ok ? st : (st | KBL_ST_ASYMMETRIC);
     }
 }
 
+// A grid of up to 4096 workgroups walks the active list (its length is on
+// the device): a few per CU at a time, each taking every 4096th entry.
 template <int D, int BX, int BY, int TX, int TY, bool F32 = false>
 hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
-    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY, F32>), dim3(bounds_grid(a.f)),
+    const int64_t g = a.f.n_elem < 4096 ? a.f.n_elem : 4096;
+    hipLaunchKernelGGL((bounds_bwd_fp64<D, BX, BY, TX, TY, F32>), dim3((unsigned)g),
                        dim3(BX * BY), 0, stream, a);
     return hipGetLastError();
 }
@@ -507,15 +522,16 @@ hipError_t launch_bwd(const BwdArgs& a, hipStream_t stream) {
 }  // namespace
 
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
-                                  double* slot, double* grad_states, uint32_t* status, int dim,
-                                  bool mixed, hipStream_t stream) {
+                                  const ActiveSet& act, double* slot, double* grad_states,
+                                  uint32_t* status, int dim, bool mixed, hipStream_t stream) {
     if (f.n_elem == 0) return hipSuccess;
     BwdArgs a;
     a.f = f;
     a.fstatus = fstatus;
     a.gbnd = gbnd;
+    a.act_count = act.count;
+    a.act_list = act.list;
     a.slot = slot;
-    a.status = status;
     hipError_t err;
     if (dim == 2 && mixed) {
         const int n = f.nx > f.ny ? f.nx : f.ny;
@@ -543,13 +559,17 @@ hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, 
     if (err != hipSuccess) return err;
     const int64_t blocks = (f.n_nodes + 255) / 256;
     const unsigned g = (unsigned)(blocks < 65535 * 16 ? blocks : 65535 * 16);
-    if (dim == 2) hipLaunchKernelGGL(gather_slots<2>, dim3(g), dim3(256), 0, stream, f, slot, grad_states);
-    else hipLaunchKernelGGL(gather_slots<1>, dim3(g), dim3(256), 0, stream, f, slot, grad_states);
+    if (dim == 2)
+        hipLaunchKernelGGL(gather_slots<2>, dim3(g), dim3(256), 0, stream, f, slot, act.flag,
+                           grad_states);
+    else
+        hipLaunchKernelGGL(gather_slots<1>, dim3(g), dim3(256), 0, stream, f, slot, act.flag,
+                           grad_states);
     err = hipGetLastError();
     if (err != hipSuccess || !status) return err;
     const int64_t eb = (f.n_elem + 255) / 256;
-    hipLaunchKernelGGL(check_symmetric, dim3((unsigned)(eb < 65535 * 16 ? eb : 65535 * 16)),
-                       dim3(256), 0, stream, f, status);
+    hipLaunchKernelGGL(bwd_status, dim3((unsigned)(eb < 65535 * 16 ? eb : 65535 * 16)),
+                       dim3(256), 0, stream, f, fstatus, status);
     return hipGetLastError();
 }
 

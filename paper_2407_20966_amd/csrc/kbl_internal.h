@@ -100,15 +100,24 @@ bool mixed_tile_fits_2d(int tile, int nx, int ny);
 hipError_t launch_bounds_mixed(const BoundsArgs& a, int precision, hipStream_t stream, int tile);
 hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream);
 hipError_t launch_riemann_fp64(const RiemannArgs& a, int dim, hipStream_t stream);
-// Bounds backward + gather.  mixed: winners from the FP32 envelopes of the
-// mixed-precision forward (2D only); everything else stays FP64.
+// The elements whose bounds' adjoint is nonzero (a bound binds the limiter):
+// the limiter's adjoint appends them to `list` (order unspecified: nothing
+// computed from the list depends on it) and sets flag[e] for every element.
+struct ActiveSet {
+    uint32_t* count;   // [1] number listed (the limiter's adjoint clears it first)
+    int32_t* list;     // [n_elem]
+    uint8_t* flag;     // [n_elem] 1 if listed, else 0
+};
+// Bounds backward over the listed elements, gather and status.  mixed:
+// winners from the FP32 envelopes of the mixed-precision forward (2D only);
+// everything else stays FP64.
 hipError_t launch_bounds_bwd_fp64(const BoundsArgs& f, const uint32_t* fstatus, const double* gbnd,
-                                  double* slot, double* grad_states, uint32_t* status, int dim,
-                                  bool mixed, hipStream_t stream);
+                                  const ActiveSet& act, double* slot, double* grad_states,
+                                  uint32_t* status, int dim, bool mixed, hipStream_t stream);
 // Per-bit counts of n status words into counts[32] (cleared first).
 hipError_t launch_status_summary(const uint32_t* st, int64_t n, uint64_t* counts,
                                  hipStream_t stream);
 hipError_t launch_limit_bwd_fp64(const LimitArgs& a, int dim, const double* grad, double* gsol,
-                                 double* gbnd, hipStream_t stream);
+                                 double* gbnd, const ActiveSet& act, hipStream_t stream);
 
 }  // namespace kbl

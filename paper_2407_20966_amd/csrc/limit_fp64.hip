@@ -264,7 +264,8 @@ __device__ __forceinline__ int grp_first(bool hit, int j) {
 // node / variable.  Writes dJ/dsolution per node and dJ/dbounds per element.
 template <int D, int G>
 __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const double* grad,
-                                                           double* gsol, double* gbnd) {
+                                                           double* gsol, double* gbnd,
+                                                           ActiveSet act) {
     constexpr int NV = D + 2;
     constexpr int EPB = kThreads / G;
     const int tid = threadIdx.x;
@@ -415,29 +416,49 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
             }
         }
     }
+    // Elements with a nonzero bounds' adjoint (bit test: +-0 stays out, a NaN
+    // is listed) go on the active list: one atomic per wave, each listed
+    // element at the wave's base plus its rank among the wave's listed lanes.
+    const bool head = j == 0 && e < p.n_elem;
+    const bool listed = head && !bad_b && vstar >= 0 &&
+                        ((uint64_t)__double_as_longlong(gb_term) << 1) != 0;
+    if (head) act.flag[e] = listed ? 1 : 0;
+    const uint64_t m = __ballot(listed);
+    if (m) {
+        const int lane = threadIdx.x & 63;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(act.count, (uint32_t)__popcll(m));
+        base = __shfl(base, leader, 64);
+        if (listed) act.list[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)e;
+    }
+}
+
+__global__ void clear_count(uint32_t* count) {
+    if (threadIdx.x == 0) *count = 0;
 }
 
 template <int D, int G>
 hipError_t launch_bwd_g(const LimitArgs& a, const double* grad, double* gsol, double* gbnd,
-                        hipStream_t stream) {
+                        const ActiveSet& act, hipStream_t stream) {
     constexpr int EPB = kThreads / G;
     const int64_t blocks = (a.n_elem + EPB - 1) / EPB;
     if (blocks > (int64_t)INT32_MAX) return hipErrorInvalidValue;
     hipLaunchKernelGGL((limit_bwd_fp64<D, G>), dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                       a, grad, gsol, gbnd);
+                       a, grad, gsol, gbnd, act);
     return hipGetLastError();
 }
 
 template <int D>
 hipError_t launch_bwd_d(const LimitArgs& a, const double* grad, double* gsol, double* gbnd,
-                        hipStream_t stream) {
-    if (a.n_s <= 1) return launch_bwd_g<D, 1>(a, grad, gsol, gbnd, stream);
-    if (a.n_s <= 2) return launch_bwd_g<D, 2>(a, grad, gsol, gbnd, stream);
-    if (a.n_s <= 4) return launch_bwd_g<D, 4>(a, grad, gsol, gbnd, stream);
-    if (a.n_s <= 8) return launch_bwd_g<D, 8>(a, grad, gsol, gbnd, stream);
-    if (a.n_s <= 16) return launch_bwd_g<D, 16>(a, grad, gsol, gbnd, stream);
-    if (a.n_s <= 32) return launch_bwd_g<D, 32>(a, grad, gsol, gbnd, stream);
-    return launch_bwd_g<D, 64>(a, grad, gsol, gbnd, stream);
+                        const ActiveSet& act, hipStream_t stream) {
+    if (a.n_s <= 1) return launch_bwd_g<D, 1>(a, grad, gsol, gbnd, act, stream);
+    if (a.n_s <= 2) return launch_bwd_g<D, 2>(a, grad, gsol, gbnd, act, stream);
+    if (a.n_s <= 4) return launch_bwd_g<D, 4>(a, grad, gsol, gbnd, act, stream);
+    if (a.n_s <= 8) return launch_bwd_g<D, 8>(a, grad, gsol, gbnd, act, stream);
+    if (a.n_s <= 16) return launch_bwd_g<D, 16>(a, grad, gsol, gbnd, act, stream);
+    if (a.n_s <= 32) return launch_bwd_g<D, 32>(a, grad, gsol, gbnd, act, stream);
+    return launch_bwd_g<D, 64>(a, grad, gsol, gbnd, act, stream);
 }
 
 template <int D, int G>
@@ -469,10 +490,13 @@ hipError_t launch_limit_fp64(const LimitArgs& a, int dim, hipStream_t stream) {
 }
 
 hipError_t launch_limit_bwd_fp64(const LimitArgs& a, int dim, const double* grad, double* gsol,
-                                 double* gbnd, hipStream_t stream) {
-    if (a.n_elem == 0) return hipSuccess;
-    return dim == 2 ? launch_bwd_d<2>(a, grad, gsol, gbnd, stream)
-                    : launch_bwd_d<1>(a, grad, gsol, gbnd, stream);
+                                 double* gbnd, const ActiveSet& act, hipStream_t stream) {
+    // the count is cleared by a kernel (capturable; no memset node)
+    hipLaunchKernelGGL(clear_count, dim3(1), dim3(64), 0, stream, act.count);
+    hipError_t err = hipGetLastError();
+    if (err != hipSuccess || a.n_elem == 0) return err;
+    return dim == 2 ? launch_bwd_d<2>(a, grad, gsol, gbnd, act, stream)
+                    : launch_bwd_d<1>(a, grad, gsol, gbnd, act, stream);
 }
 
 }  // namespace kbl

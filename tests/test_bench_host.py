@@ -75,3 +75,44 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _counter_csv(path, counter, rows):
+    cols = ["Correlation_Id", "Dispatch_Id", "Agent_Id", "Queue_Id", "Process_Id", "Thread_Id",
+            "Grid_Size", "Kernel_Id", "Kernel_Name", "Workgroup_Size", "Counter_Name",
+            "Counter_Value"]
+    with open(path, "w") as fh:
+        fh.write(",".join(f'"{c}"' for c in cols) + "\n")
+        for i, (name, grid, value) in enumerate(rows, 1):
+            fh.write(f'{i},{i},"Agent 1",1,1,1,{grid},7,"{name}",256,"{counter}",{value}\n')
+
+
+def test_write_traffic_from_counter_csvs(tmp_path, monkeypatch):
+    """The traffic entry comes from the two counter runs: the copy calibrates
+    FETCH_SIZE (reads = writes), the last FP64 bounds launch is the profiled
+    one (autotuner candidates at the same grid come earlier), and an entry of
+    the same workload, kernel and grid is replaced, others kept."""
+    (tmp_path / "profiles").mkdir()
+    tf = tmp_path / bench.TRAFFIC_FILE
+    tf.write_text("# header\n\n[entry]\nworkload = other\nkernel = k\ngrid_threads = 1\n")
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_sources_sha", lambda dim: "ab" * 32)
+    k_cand = "void kbl::(anonymous namespace)::bounds_fp64_1d<64, 1>(kbl::BoundsArgs)"
+    k_main = "void kbl::(anonymous namespace)::bounds_fp64_1d<256, 1>(kbl::BoundsArgs)"
+    copy = "__amd_rocclr_copyBuffer"
+    _counter_csv(tmp_path / "f.csv", "FETCH_SIZE",
+                 [(copy, 1024, 500.0), (k_cand, 64 * 64, 9.0), (k_main, 64 * 256, 30.0),
+                  (k_main, 64 * 256, 34.0)])
+    _counter_csv(tmp_path / "w.csv", "WRITE_SIZE",
+                 [(copy, 1024, 1000.0), (k_cand, 64 * 64, 1.0), (k_main, 64 * 256, 3.0),
+                  (k_main, 64 * 256, 5.0)])
+    for _ in range(2):                                   # the second call replaces the entry
+        e = bench.write_traffic("line64", str(tmp_path / "f.csv"), str(tmp_path / "w.csv"))
+    assert e["kernel"] == "bounds_fp64_1d<256, 1>" and e["grid_threads"] == str(64 * 256)
+    assert float(e["fetch_scale"]) == pytest.approx(2.0)
+    assert float(e["bytes_per_launch"]) == pytest.approx((32.0 * 2.0 + 4.0) * 1024.0)
+    # line64: 64 elements x 4 nodes x 3 variables read, rowptr, 3-element rows, bounds, status
+    assert int(e["algorithmic_bytes_per_launch"]) == 64 * 4 * 3 * 8 + 65 * 4 + 192 * 4 + 6 * 64 * 8 + 64 * 4
+    text = tf.read_text()
+    assert text.count("[entry]") == 2 and "workload = other" in text
+    assert text.startswith("# header")
