@@ -40,6 +40,8 @@
 //     to this element's stencil slots.
 // A gather kernel then sums, for each node, the slots of listed elements that
 // refer to it, walking the (symmetric) stencil in CSR order.
+#include <type_traits>
+
 #include "bounds_common.h"
 
 namespace kbl {
@@ -189,6 +191,20 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
         for (int i = 0; i < TX; ++i)
 #pragma unroll
             for (int j = 0; j < TY; ++j) wn[0][i][j] = wn[1][i][j] = wn[2][i][j] = wn[3][i][j] = 0;
+        // Envelopes whose adjoint weight is identically zero are not formed:
+        // env 0/1 (min/max of g) carry the rho, m and E bounds, env 2/3 (min/max
+        // of g_I) the E bounds only (eq. Ebounds).  The limiter's adjoint gives
+        // one binding bound, so mostly one or two envelopes are needed.
+        auto nz = [](double v) { return ((uint64_t)__double_as_longlong(v) << 1) != 0; };
+        bool gm = false;
+#pragma unroll
+        for (int k = 0; k < D; ++k) gm = gm || nz(gb[1 + k]) || nz(gb[NV + 1 + k]);
+        const int need = ((nz(gb[0]) || nz(gb[D + 1]) || gm) ? 1 : 0) |
+                         ((nz(gb[NV]) || nz(gb[NV + D + 1]) || gm) ? 2 : 0) |
+                         (nz(gb[D + 1]) ? 4 : 0) | (nz(gb[NV + D + 1]) ? 8 : 0);
+        // the loop variant: the smallest of {1, 2, 3, 5, 10, 15} covering `need`
+        const int mask = need == 1 ? 1 : need == 2 ? 2 : (need & ~3) == 0 ? 3
+                       : (need & ~5) == 0 ? 5 : (need & ~10) == 0 ? 10 : 15;
         if (!F32) {
 #pragma unroll
             for (int i = 0; i < TX; ++i)
@@ -202,40 +218,57 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
             const bool has_i = p.half_delta > 0.0;
             const double kt = ref[0] + 1.0;
             const double ki = has_i ? ref[1] + 1.0 : 0.0;
-            for (int s = 0; s < (int)S; ++s) {
-                const Coef c = sC[s];
-                const double at = c.a - kt;
-                const double ai = has_i ? c.al - ki : -1e300;
-                double A[TX], AI[TX], B[TY];
+            auto envelopes = [&](auto mc) {
+                constexpr int M = decltype(mc)::value;
+                for (int s = 0; s < (int)S; ++s) {
+                    const Coef c = sC[s];
+                    const double at = c.a - kt;
+                    const double ai = has_i ? c.al - ki : -1e300;
+                    double A[TX], AI[TX], B[TY];
 #pragma unroll
-                for (int i = 0; i < TX; ++i) {
-                    const double d = ux[i] - c.ux;
-                    const double t = c.nk * d;
-                    A[i] = fma(t, d, at);
-                    AI[i] = fma(t, d, ai);
-                }
-#pragma unroll
-                for (int j = 0; j < TY; ++j) {
-                    const double d = uy[j] - c.uy;
-                    B[j] = D == 2 ? (c.nk * d) * d : 0.0;
-                }
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
+                    for (int i = 0; i < TX; ++i) {
+                        const double d = ux[i] - c.ux;
+                        const double t = c.nk * d;
+                        if (M & 3) A[i] = fma(t, d, at);
+                        if (M & 12) AI[i] = fma(t, d, ai);
+                    }
 #pragma unroll
                     for (int j = 0; j < TY; ++j) {
-                        const double qt = keyed(A[i] + B[j], s), qi = keyed(AI[i] + B[j], s);
-                        q[0][i][j] = fmin(q[0][i][j], qt);
-                        q[1][i][j] = fmax(q[1][i][j], qt);
-                        q[2][i][j] = fmin(q[2][i][j], qi);
-                        q[3][i][j] = fmax(q[3][i][j], qi);
+                        const double d = uy[j] - c.uy;
+                        B[j] = D == 2 ? (c.nk * d) * d : 0.0;
                     }
+#pragma unroll
+                    for (int i = 0; i < TX; ++i)
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            if (M & 3) {
+                                const double qt = keyed(A[i] + B[j], s);
+                                if (M & 1) q[0][i][j] = fmin(q[0][i][j], qt);
+                                if (M & 2) q[1][i][j] = fmax(q[1][i][j], qt);
+                            }
+                            if (M & 12) {
+                                const double qi = keyed(AI[i] + B[j], s);
+                                if (M & 4) q[2][i][j] = fmin(q[2][i][j], qi);
+                                if (M & 8) q[3][i][j] = fmax(q[3][i][j], qi);
+                            }
+                        }
+                }
+            };
+            switch (mask) {
+                case 1: envelopes(std::integral_constant<int, 1>{}); break;
+                case 2: envelopes(std::integral_constant<int, 2>{}); break;
+                case 3: envelopes(std::integral_constant<int, 3>{}); break;
+                case 5: envelopes(std::integral_constant<int, 5>{}); break;
+                case 10: envelopes(std::integral_constant<int, 10>{}); break;
+                default: envelopes(std::integral_constant<int, 15>{}); break;
             }
 #pragma unroll
             for (int env = 0; env < 4; ++env)
 #pragma unroll
                 for (int i = 0; i < TX; ++i)
 #pragma unroll
-                    for (int j = 0; j < TY; ++j) wn[env][i][j] = key_index(q[env][i][j]);
+                    for (int j = 0; j < TY; ++j)
+                        wn[env][i][j] = ((mask >> env) & 1) ? key_index(q[env][i][j]) : kNoKey;
         } else {
             // winners from the FP32 envelopes; their FP64 log values are then
             // recomputed from the FP64 coefficients of the winning states
@@ -319,6 +352,11 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
                 double Jt = 0.0, dJdu[2] = {0.0, 0.0};
 #pragma unroll
                 for (int env = 0; env < 4; ++env) {
+                    if (!((mask >> env) & 1)) {          // zero adjoint weight
+                        q[env][i][j] = 0.0;
+                        wn[env][i][j] = kNoKey;
+                        continue;
+                    }
                     // the winner's log value in FP64, as the forward forms it
                     const Coef& c = sC[wn[env][i][j]];
                     const double dx = u[0] - c.ux;
