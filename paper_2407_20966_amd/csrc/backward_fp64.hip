@@ -315,118 +315,117 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(KBL_BWD
             }
             // (the FP64 log values of the winners are recomputed per node below)
         }
-        // per node: adjoint weights, envelope shares (q is overwritten with
-        // M Phi f) and the box-end adjoints; nodes outside the grid retire
-        double gl[2] = {0.0, 0.0}, gh[2] = {0.0, 0.0};
-        int lk = kNoKey;                 // smallest winner still to be summed
+        // the winners, one byte per envelope (S <= 256 states)
+        uint32_t pk[TX][TY];
 #pragma unroll
         for (int i = 0; i < TX; ++i)
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                const int x = TX * tx + i, y = TY * ty + j;
-                const bool valid = x < p.nx && (D == 1 || y < p.ny);
-                const double u[2] = {ux[i], uy[j]};
-                double M = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
-                if (D == 2) M *= hy * ((y == 0 || y == p.ny - 1) ? 0.5 : 1.0);
-                if (!valid) M = 0.0;
-                double hu2 = 0.5 * u[0] * u[0];
-                if (D == 2) hu2 += 0.5 * u[1] * u[1];
-                double phi[4], dphi[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
-                phi[0] = rm * (gb[0] + gb[D + 1] * hu2);
-                phi[1] = rp * (gb[NV] + gb[NV + D + 1] * hu2);
-                phi[2] = rm * gb[D + 1];
-                phi[3] = rp * gb[NV + D + 1];
+            for (int j = 0; j < TY; ++j)
+                pk[i][j] = (uint32_t)(wn[0][i][j] & 0xff) | ((uint32_t)(wn[1][i][j] & 0xff) << 8) |
+                           ((uint32_t)(wn[2][i][j] & 0xff) << 16) |
+                           ((uint32_t)(wn[3][i][j] & 0xff) << 24);
+        // Envelope by envelope (only those with a nonzero adjoint weight): per
+        // node the adjoint weight Phi of the moment rows, the share M Phi f of
+        // the winner and the box-end adjoint; then, per wave and winner in
+        // increasing state order, the shares and their moments about the
+        // winner's mean velocity, added to the wave's sums in envelope order
+        // (no barriers inside; deterministic).
+        double gl[2] = {0.0, 0.0}, gh[2] = {0.0, 0.0};
+        const double inv_n1[2] = {1.0 / (double)(p.nx - 1), D == 2 ? 1.0 / (double)(p.ny - 1) : 0.0};
+        const double inv_w[2] = {1.0 / (hx * (p.nx - 1)), D == 2 ? 1.0 / (hy * (p.ny - 1)) : 0.0};
 #pragma unroll
-                for (int k = 0; k < D; ++k) {
-                    const double gmin = gb[1 + k], gmax = gb[NV + 1 + k];
-                    if (u[k] < 0.0) {
-                        phi[1] += rp * gmin * u[k]; phi[0] += rm * gmax * u[k];
-                        dphi[1][k] += rp * gmin; dphi[0][k] += rm * gmax;
+        for (int env = 0; env < 4; ++env) {
+            if (!((mask >> env) & 1)) continue;                  // zero adjoint weight
+            const bool upper = env & 1, internal = env >= 2;
+            const double r = upper ? rp : rm;
+            const int b0 = upper ? NV : 0;                         // rho row of this side
+            int w[TX][TY];
+            double wv[TX][TY];
+            int lk = kNoKey;                                       // smallest winner left
+#pragma unroll
+            for (int i = 0; i < TX; ++i)
+#pragma unroll
+                for (int j = 0; j < TY; ++j) {
+                    const int x = TX * tx + i, y = TY * ty + j;
+                    const bool valid = x < p.nx && (D == 1 || y < p.ny);
+                    const double u[2] = {ux[i], uy[j]};
+                    double M = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
+                    if (D == 2) M *= hy * ((y == 0 || y == p.ny - 1) ? 0.5 : 1.0);
+                    if (!valid) M = 0.0;
+                    // Phi: density + energy rows, and the momentum rows split
+                    // by the sign of u (the lower bound takes the upper
+                    // envelope where u < 0); g_I only enters the energy
+                    double phi, dphi[2] = {0.0, 0.0};
+                    if (!internal) {
+                        double hu2 = 0.5 * u[0] * u[0];
+                        if (D == 2) hu2 += 0.5 * u[1] * u[1];
+                        phi = r * (gb[b0] + gb[b0 + D + 1] * hu2);
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {
+                            const double gmin = gb[1 + k], gmax = gb[NV + 1 + k];
+                            const double gk = (u[k] < 0.0) == upper ? gmin : gmax;
+                            phi += r * gk * u[k];
+                            dphi[k] = r * gk;
+                            dphi[k] += r * gb[b0 + D + 1] * u[k];
+                        }
                     } else {
-                        phi[0] += rm * gmin * u[k]; phi[1] += rp * gmax * u[k];
-                        dphi[0][k] += rm * gmin; dphi[1][k] += rp * gmax;
-                    }
-                    dphi[0][k] += rm * gb[D + 1] * u[k];
-                    dphi[1][k] += rp * gb[NV + D + 1] * u[k];
-                }
-                double Jt = 0.0, dJdu[2] = {0.0, 0.0};
-#pragma unroll
-                for (int env = 0; env < 4; ++env) {
-                    if (!((mask >> env) & 1)) {          // zero adjoint weight
-                        q[env][i][j] = 0.0;
-                        wn[env][i][j] = kNoKey;
-                        continue;
+                        phi = r * gb[b0 + D + 1];
                     }
                     // the winner's log value in FP64, as the forward forms it
-                    const Coef& c = sC[wn[env][i][j]];
+                    const int sw = (int)((pk[i][j] >> (8 * env)) & 0xff);
+                    const Coef& c = sC[sw];
                     const double dx = u[0] - c.ux;
-                    double qv = fma(c.nk * dx, dx, env >= 2 ? c.al : c.a);
+                    double qv = fma(c.nk * dx, dx, internal ? c.al : c.a);
                     if (D == 2) {
                         const double dy = u[1] - c.uy;
                         qv += (c.nk * dy) * dy;
                     }
                     const double f = exp(qv);
-                    const double wf = M * phi[env] * f;
-                    Jt += wf;
-                    const double cu[2] = {c.ux, c.uy};
+                    const double wf = M * phi * f;
+                    if (p.grid_mode == KBL_GRID_STENCIL && valid) {
+                        const int t[2] = {x, y};
+                        const double cu[2] = {c.ux, c.uy};
 #pragma unroll
-                    for (int k = 0; k < D; ++k)
-                        dJdu[k] += M * dphi[env][k] * f + wf * 2.0 * c.nk * (u[k] - cu[k]);
-                    q[env][i][j] = wf;
-                    if (!valid) wn[env][i][j] = kNoKey;
-                    lk = min(lk, wn[env][i][j]);
-                }
-                if (p.grid_mode == KBL_GRID_STENCIL && valid) {
-                    const int t[2] = {x, y};
-                    const int n[2] = {p.nx, p.ny};
-                    const double h[2] = {hx, hy};
-#pragma unroll
-                    for (int k = 0; k < D; ++k) {
-                        const double fr = (double)t[k] / (double)(n[k] - 1);
-                        gl[k] += dJdu[k] * (1.0 - fr) - Jt / (h[k] * (n[k] - 1));
-                        gh[k] += dJdu[k] * fr + Jt / (h[k] * (n[k] - 1));
+                        for (int k = 0; k < D; ++k) {
+                            const double dJdu = M * dphi[k] * f + wf * 2.0 * c.nk * (u[k] - cu[k]);
+                            const double fr = (double)t[k] * inv_n1[k];
+                            const double jw = wf * inv_w[k];
+                            gl[k] += dJdu * (1.0 - fr) - jw;
+                            gh[k] += dJdu * fr + jw;
+                        }
                     }
+                    wv[i][j] = wf;
+                    w[i][j] = valid ? sw : kNoKey;
+                    lk = min(lk, w[i][j]);
                 }
-                __builtin_amdgcn_sched_barrier(0);
+            for (;;) {
+                const int s = wave_min_i32(lk);
+                if (s == kNoKey) break;
+                const Coef c = sC[s];
+                double z[4] = {0.0, 0.0, 0.0, 0.0};
+                int nlk = kNoKey;
+#pragma unroll
+                for (int i = 0; i < TX; ++i)
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) {
+                        // the node's share if s won it, selected by a 0/1
+                        // factor (shares are finite: M = 0 outside the grid)
+                        const bool m = w[i][j] == s;
+                        const double wf = (m ? 1.0 : 0.0) * wv[i][j];
+                        w[i][j] = m ? kNoKey : w[i][j];
+                        nlk = min(nlk, w[i][j]);
+                        const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
+                        const double d2 = dx * dx + dy * dy;
+                        z[0] += wf;
+                        z[1] = fma(wf, dx, z[1]);
+                        if (D == 2) z[2] = fma(wf, dy, z[2]);
+                        z[3] = fma(wf, d2, z[3]);
+                    }
+                lk = nlk;
+                double zz[8] = {z[0], z[1], z[2], z[3], internal ? z[0] : 0.0, 0.0, 0.0, 0.0};
+                const double zs = wave_transpose8<OpSum>(zz);   // lane l: sum k = l / 8
+                if ((lane & 7) == 0 && (lane >> 3) < 5) sZw[wid][s][lane >> 3] += zs;
             }
-        // per wave, winner by winner in increasing order: sum the shares and
-        // their moments about the winner's mean velocity (no barriers inside)
-        for (;;) {
-            const int s = wave_min_i32(lk);
-            if (s == kNoKey) break;
-            const Coef c = sC[s];
-            double z[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            int nlk = kNoKey;
-#pragma unroll
-            for (int i = 0; i < TX; ++i)
-#pragma unroll
-                for (int j = 0; j < TY; ++j) {
-                    // the node's shares won by s: distribution envelopes (wt)
-                    // and internal ones (wi), selected by a 0/1 factor (the
-                    // shares are finite: M = 0 outside the grid)
-                    double wt = 0.0, wi = 0.0;
-#pragma unroll
-                    for (int env = 0; env < 4; ++env) {
-                        const bool m = wn[env][i][j] == s;
-                        const double sel = m ? 1.0 : 0.0;
-                        if (env < 2) wt = fma(sel, q[env][i][j], wt);
-                        else         wi = fma(sel, q[env][i][j], wi);
-                        wn[env][i][j] = m ? kNoKey : wn[env][i][j];
-                        nlk = min(nlk, wn[env][i][j]);
-                    }
-                    const double dx = ux[i] - c.ux, dy = D == 2 ? uy[j] - c.uy : 0.0;
-                    const double d2 = dx * dx + dy * dy;
-                    const double wf = wt + wi;
-                    z[0] += wf;
-                    z[1] = fma(wf, dx, z[1]);
-                    if (D == 2) z[2] = fma(wf, dy, z[2]);
-                    z[3] = fma(wf, d2, z[3]);
-                    z[4] += wi;
-                }
-            lk = nlk;
-            double zz[8] = {z[0], z[1], z[2], z[3], z[4], 0.0, 0.0, 0.0};
-            const double zs = wave_transpose8<OpSum>(zz);   // lane l: sum k = l / 8
-            if ((lane & 7) == 0 && (lane >> 3) < 5) sZw[wid][s][lane >> 3] = zs;
         }
         double ext[4] = {gl[0], gh[0], gl[1], gh[1]};
         block_sum_t<NT, 4>(ext, red);    // valid in thread 0; contains the barriers
