@@ -417,20 +417,30 @@ __global__ __launch_bounds__(kThreads) void limit_bwd_fp64(LimitArgs p, const do
         }
     }
     // Elements with a nonzero bounds' adjoint (bit test: +-0 stays out, a NaN
-    // is listed) go on the active list: one atomic per wave, each listed
-    // element at the wave's base plus its rank among the wave's listed lanes.
+    // is listed) go on the active list: one atomic per workgroup, each listed
+    // element at the workgroup's base plus the listed lanes of the waves
+    // before it plus its rank among its wave's listed lanes.
     const bool head = j == 0 && e < p.n_elem;
     const bool listed = head && !bad_b && vstar >= 0 &&
                         ((uint64_t)__double_as_longlong(gb_term) << 1) != 0;
     if (head) act.flag[e] = listed ? 1 : 0;
+    constexpr int NW = kThreads / 64;
+    __shared__ uint32_t wcount[NW + 1];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const uint64_t m = __ballot(listed);
-    if (m) {
-        const int lane = threadIdx.x & 63;
-        const int leader = __ffsll((unsigned long long)m) - 1;
-        uint32_t base = 0;
-        if (lane == leader) base = atomicAdd(act.count, (uint32_t)__popcll(m));
-        base = __shfl(base, leader, 64);
-        if (listed) act.list[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)e;
+    if (lane == 0) wcount[wid] = (uint32_t)__popcll(m);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t t = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) t += wcount[w];
+        wcount[NW] = t ? atomicAdd(act.count, t) : 0u;
+    }
+    __syncthreads();
+    if (listed) {
+        uint32_t base = wcount[NW];
+        for (int w = 0; w < wid; ++w) base += wcount[w];
+        act.list[base + __popcll(m & ((1ull << lane) - 1))] = (int32_t)e;
     }
 }
 
