@@ -710,9 +710,10 @@ def backward_leg(args, kbl, torch, synth, stream, name="quad512"):
             bstep()
         e1.record(stream)
         torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / steps, res[0] + res[1]
+        return e0.elapsed_time(e1) / steps, res
 
-    bms, gref = time_backward(prm)
+    bms, res = time_backward(prm)
+    gref = res[0] + res[1]
     frac = limited_fraction(prm, d.tg)
     # the forward step again after the backward timings; the reference is
     # the faster of the two (a slow outlier makes the ratio look better)
@@ -726,9 +727,14 @@ def backward_leg(args, kbl, torch, synth, stream, name="quad512"):
     # the bounds adjoint, which the default target exercises only where the
     # limiter binds.
     tg_dense = d.st + 1e4 * (d.tg - d.st)
-    dms, _ = time_backward(prm, tg_dense)
+    dms, dres = time_backward(prm, tg_dense)
+    # elements per binding bound: the nonzero entry of each row of dJ/dbounds
+    rows = ["rho_min"] + [f"m{j}_min" for j in range(wl.dim)] + ["E_min", "rho_max"] + \
+           [f"m{j}_max" for j in range(wl.dim)] + ["E_max"]
+    binding = dict(zip(rows, (dres[2] != 0).sum(dim=1).tolist()))
     dense = {"ms_per_call": dms, "vs_forward_step": dms / ms_fwd,
              "limited_fraction": limited_fraction(prm, tg_dense),
+             "elements_per_binding_bound": binding,
              "what": "the same call with every element limited: target = states + "
                      "1e4 (target - states)"}
     del tg_dense
@@ -748,7 +754,8 @@ def backward_leg(args, kbl, torch, synth, stream, name="quad512"):
           f"{100 * frac:.1f}% of the elements limited)", file=sys.stderr, flush=True)
     if not args.no_mixed:
         prm_m = kbl.make_params(wl.gamma, r_fac=wl.r_fac, precision=kbl.PREC_MIXED_FP32)
-        mms, gmix = time_backward(prm_m)
+        mms, mres = time_backward(prm_m)
+        gmix = mres[0] + mres[1]
         scale = float(gref.abs().max())
         diff = (gmix - gref).abs()
         out["mixed_fp32"] = {
