@@ -188,6 +188,22 @@ def _quad_geometry(N: int, p: int):
     return X, Y, w2, cols, rowptr
 
 
+def quad_block_stencils(N: int, r: int):
+    """CSR rows of a periodic N x N quad mesh listing every element within r
+    cells in each direction, self first: (2r + 1)^2 elements per row."""
+    rows = []
+    for e in range(N * N):
+        ey, ex = divmod(e, N)
+        row = [e]
+        for dy in range(-r, r + 1):
+            for dx in range(-r, r + 1):
+                if dx or dy:
+                    row.append(((ey + dy) % N) * N + (ex + dx) % N)
+        rows.append(row)
+    rowptr = np.concatenate([[0], np.cumsum([len(x) for x in rows])]).astype(np.int32)
+    return rowptr, np.concatenate(rows).astype(np.int32)
+
+
 def make_quad_workload(N: int = 256, p: int = 3, seed: int = BASE_SEED + 1,
                        field_kind: str = "riemann4", grid_nodes: int = 48,
                        grid_mode: int = GRID_STENCIL, k: float = 4.0,

@@ -185,6 +185,39 @@ def test_duplicate_stencil_entries(kbl, N):
     compare_with_oracle(kbl, wl)
 
 
+def test_stencils_beyond_256_states_are_flagged(kbl):
+    """The backward keeps at most 256 stencil states in LDS: elements with
+    larger stencils get KBL_ST_TOO_LARGE and their states no gradient through
+    their bounds, while the limiter's part of the gradient (d/dsolution,
+    d/dbounds) is still complete."""
+    from synth.workloads import quad_block_stencils
+    wl = synth.make_quad_workload(N=6, seed=15, grid_nodes=24, name="b_big")
+    wl.rowptr, wl.cols = quad_block_stencils(6, 2)
+    wl.target = wl.states + 10.0 * (wl.target - wl.states)
+    G = np.random.default_rng(6).standard_normal(wl.target.shape)
+    gst, gsol, gb, st = gpu_backward(kbl, wl, G)
+    assert np.all(st & kbl.ST_TOO_LARGE)
+    assert np.isfinite(gst).all()
+    rsol, _, rgb = oracle.workload_backward(wl, G)
+
+    def on_gpu(w):
+        r = gpu_backward(kbl, w, G)
+        return r[1], r[2]
+
+    def on_oracle(w):
+        r = oracle.workload_backward(w, G)
+        return r[0], r[2]
+
+    sp_g = rounding_spread(on_gpu, wl, (gsol, gb))
+    sp_o = rounding_spread(on_oracle, wl, (rsol, rgb))
+    assert np.abs(gb).max() > 0
+    for a, b, k, sg, so in ((gsol, rsol, wl.n_s, sp_g[0], sp_o[0]),
+                            (gb, rgb, 1, sp_g[1], sp_o[1])):
+        scale = dof_scale(b, k)
+        bar = np.maximum(1e-12, 4.0 * (sg + so) / scale)
+        assert (np.abs(a - b) / scale / bar).max() <= 1.0
+
+
 def test_quad512_finite_differences(kbl):
     """Config of the differentiation form: full 512^2 mesh, 200 DoFs."""
     wl = synth.make_workload("quad512")

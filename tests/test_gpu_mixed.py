@@ -11,7 +11,7 @@ import pytest
 
 import oracle
 import synth
-from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec
+from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec, quad_block_stencils
 from tests._parity import bounds_error, element_value_scale, limited_error, stencil_momentum_scale
 
 torch = pytest.importorskip("torch")
@@ -223,3 +223,27 @@ def test_mixed_determinism(kbl):
         a, _ = gpu_bounds(kbl, wl, prec)
         b, _ = gpu_bounds(kbl, wl, prec)
         assert np.array_equal(a.view(np.uint8), b.view(np.uint8))
+
+
+def test_mixed_stencils_beyond_256_states_are_flagged(kbl):
+    """The mixed kernel keeps at most 256 stencil states in LDS: larger
+    stencils get KBL_ST_TOO_LARGE and NaN bounds (the FP64 path computes
+    them), smaller ones in the same launch are unaffected."""
+    wl = synth.make_quad_workload(N=6, seed=14, grid_nodes=24, name="mq_big")
+    rp_big, cl_big = quad_block_stencils(6, 2)
+    # every other element keeps its 5-element face stencil (80 states)
+    rows = []
+    for e in range(wl.n_elem):
+        src = (wl.rowptr, wl.cols) if e % 2 else (rp_big, cl_big)
+        rows.append(src[1][src[0][e]:src[0][e + 1]])
+    wl.rowptr = np.concatenate([[0], np.cumsum([len(x) for x in rows])]).astype(np.int32)
+    wl.cols = np.concatenate(rows).astype(np.int32)
+    big = np.arange(wl.n_elem) % 2 == 0
+    for prec in (kbl.PREC_MIXED_FP32, kbl.PREC_MIXED_FP16, kbl.PREC_MIXED_BF16):
+        b, s = gpu_bounds(kbl, wl, prec)
+        assert np.all(s[big] & kbl.ST_TOO_LARGE) and np.isnan(b[:, big]).all()
+        assert not (s[~big] & kbl.ST_TOO_LARGE).any() and np.isfinite(b[:, ~big]).all()
+        rb, _ = oracle.workload_bounds(wl, elems=np.nonzero(~big)[0])
+        sel = np.nonzero(~big)[0]
+        err, _ = bounds_error(b[:, sel], rb, 2, stencil_momentum_scale(wl, sel))
+        assert err <= 1e-5, err

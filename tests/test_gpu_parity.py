@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import synth
-from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec
+from synth.workloads import GRID_GLOBAL, GRID_STENCIL, GridSpec, quad_block_stencils
 from tests._parity import (bounds_error, element_value_scale, limited_error,
                            stencil_momentum_scale)
 
@@ -211,6 +211,48 @@ def test_extreme_temperature_ratio(kbl, case):
     st[d + 1, nodes] = 1e-12 * st[0, nodes] / (wl.gamma - 1.0)
     wl.states = st
     check_workload(kbl, wl)
+
+
+def test_stencils_beyond_one_lds_chunk(kbl):
+    """25-element stencils of 16 nodes (400 states): the FP64 kernel stages
+    the coefficients in LDS in chunks of 256 states; bounds at 1e-12.  The
+    wide bounds make the pressure step (eq. pmin, eq. doublelimit) act on
+    most elements at low pressure, where the limited nodes are ill
+    conditioned: rescaling the inputs by 3 moves the oracle's own result by
+    about 1.5e-12.  The limiter is checked on the oracle's bounds against
+    1e-12 or four times the larger of that rounding spread of both sides
+    (the bar of the backward tests)."""
+    wl = synth.make_quad_workload(N=6, seed=13, grid_nodes=24, name="quad_big")
+    wl.rowptr, wl.cols = quad_block_stencils(6, 2)
+    assert (np.diff(wl.rowptr) * wl.n_s).min() > 256
+    b, s, _, _, _ = run_gpu(kbl, wl)
+    rb, rs = oracle.workload_bounds(wl)
+    err, _ = bounds_error(b, rb, wl.dim, stencil_momentum_scale(wl))
+    assert err <= TOL, f"bounds error {err:.3e}"
+    assert np.array_equal(s, rs)
+    scale = element_value_scale(wl, wl.target)
+
+    def both(f):
+        t0 = wl.target
+        wl.target = t0 * f
+        try:
+            g = run_gpu(kbl, wl, bounds_override=rb * f)
+            r = oracle.workload_limit(wl, rb * f)
+        finally:
+            wl.target = t0
+        return g[2] / f, g[4], r[0] / f, r[2]
+
+    lim, ls, rl, rls = both(1.0)
+    assert np.array_equal(ls, rls)
+    spread = np.zeros_like(rl)
+    for f in (3.0, 0.7, 1.3):
+        g, _, r, _ = both(f)
+        spread = np.maximum(spread, np.maximum(np.abs(g - lim), np.abs(r - rl)))
+    _, e = limited_error(lim, rl, scale, wl.n_s)
+    _, sp = limited_error(spread + rl, rl, scale, wl.n_s)
+    assert np.all(e <= np.maximum(TOL, 4.0 * sp)), f"limited error {e.max():.3e}"
+    print(f"[parity] quad_big: bounds err {err:.2e}, limited err {e.max():.2e} "
+          f"(spread {sp.max():.2e}), p-steps {((rls & 0x10) > 0).sum()}/{wl.n_elem}", flush=True)
 
 
 def test_single_element_stencils(kbl):
