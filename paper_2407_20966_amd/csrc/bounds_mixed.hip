@@ -29,7 +29,10 @@
 // the matrix core straight from registers.  The B operand (lane l: factor
 // l%16 at the same y nodes) is built per element in registers; the C result
 // (lane l: factor l%16 at x rows 16t + 4(l/16) + i) is contracted with X in
-// FP64.  One B-table read serves the TXW x nodes of a lane.
+// FP64.  The per-state y terms (B at each y node) come from an LDS table
+// built per chunk of states, one node column per thread, and one B-table
+// read serves the TXW x nodes of a lane; the four-wave tiles take the x
+// terms (A and A + l at each x node) from a second table built alongside.
 #include "bounds_common.h"
 
 namespace kbl {
@@ -39,7 +42,7 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kTab = 64;            // states per B-table chunk
+typedef float float2_t __attribute__((ext_vector_type(2)));
 
 // Minimum waves per SIMD the register allocator targets (1 = no constraint).
 #ifndef KBL_MIXED_WAVES
@@ -47,6 +50,7 @@ constexpr int kTab = 64;            // states per B-table chunk
 #endif
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kF16Scale = 16384.0f;            // 2^14, exact
+constexpr float kF16Log2Scale = 14.0f;
 
 // FP32 -> BF16 (and FP16) by gfx950's conversion instructions, round to
 // nearest even; BF16 -> FP32 is exact.
@@ -113,11 +117,12 @@ __device__ __forceinline__ float4_t mfma_ystage(const float* f, const YSplit<KS,
     for (int k = 0; k < KS; ++k) {
         if (CT == KBL_PREC_MIXED_FP16) {
             // both operands are scaled by 2^14 (envelopes <= 1, factors < 2)
-            // so that the low halves stay clear of FP16 subnormals
+            // so that the low halves stay clear of FP16 subnormals; the
+            // envelope values arrive scaled (the shift is in their exp2)
             half4_t ah, al;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const float av = f[4 * k + i] * kF16Scale;
+                const float av = f[4 * k + i];
                 ah[i] = (_Float16)av;
                 al[i] = (_Float16)(av - (float)ah[i]);
             }
@@ -151,15 +156,16 @@ __device__ __forceinline__ float4_t mfma_ystage(const float* f, const YSplit<KS,
 struct XF {
     double w, m, p, q;
 };
+// Nodes past the grid (the ragged tail of the last tile) get zero factors;
+// selects rather than a branch, since the lanes of a wave differ.
 __device__ __forceinline__ XF x_factors(const BoundsArgs& p, const double* box, double hx, int x) {
-    XF f = {0.0, 0.0, 0.0, 0.0};
-    if (x < p.nx) {
-        const double u = node_pos(box[0], x, hx);
-        f.w = hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0);
-        f.m = u < 0.0 ? f.w * u : 0.0;
-        f.p = u < 0.0 ? 0.0 : f.w * u;
-        f.q = f.w * u * u;
-    }
+    const bool in = x < p.nx;
+    const double u = node_pos(box[0], in ? x : p.nx - 1, hx);
+    XF f;
+    f.w = in ? hx * ((x == 0 || x == p.nx - 1) ? 0.5 : 1.0) : 0.0;
+    f.m = u < 0.0 ? f.w * u : 0.0;
+    f.p = u < 0.0 ? 0.0 : f.w * u;
+    f.q = f.w * u * u;
     return f;
 }
 
@@ -175,15 +181,30 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
     constexpr int NT = NW * 64;
     constexpr int NY = 16 * KS;     // y nodes covered
     constexpr int TY = 4 * KS;      // y nodes per lane
+    constexpr int NX = 16 * TXW * NW;   // x nodes covered
+    static_assert(NX == NY, "the tables are built by columns of a square tile");
+    constexpr int kTab = 64;            // states per table chunk
+    // The four-wave tiles (two workgroups per CU) also take the per-state x
+    // terms from LDS: measured faster there; the smaller tiles run three or
+    // more workgroups per CU, whose LDS share the table would exceed, and
+    // form them in registers.
+    constexpr bool ATAB = NW == 4;
     // the FP64 coefficients are only needed until the FP32 copies exist; the
-    // B table reuses their space
+    // tables reuse their space: B = nk (uy - Uy)^2 per (state, y node), and
+    // per (state, x node) the pair A = a + nk (ux - Ux)^2, A + l
     union Stage {
         Coef c[kMaxStates];
-        float b[kTab][NY];
+        struct {
+            float b[kTab][NY];
+            float2_t ai[ATAB ? kTab : 1][ATAB ? NX : 1];
+        } t;
     };
     __shared__ __align__(16) Stage stage;
     __shared__ CoefF sF[kMaxStates];
     __shared__ Red red;
+    // the y factors Wy {1, uy<0 ? uy : 0, uy>=0 ? uy : 0, uy^2} of the
+    // element's y nodes, zero past the grid (FP32, rounded from FP64)
+    __shared__ __align__(16) float yfac[4][NY];
 
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, xr = l & 15, g = l >> 4;
@@ -225,13 +246,27 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             f.nk = (float)c.nk;
             sF[s] = f;
         }
+        for (int t = tid; t < 4 * NY; t += NT) {
+            const int fc = t / NY, ty = t % NY;
+            float v = 0.f;
+            if (ty < p.ny) {
+                const double u = node_pos(box[2], ty, hy);
+                const double wy = hy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
+                v = (float)(fc == 0 ? wy
+                          : fc == 1 ? (u < 0.0 ? wy * u : 0.0)
+                          : fc == 2 ? (u < 0.0 ? 0.0 : wy * u)
+                                    : wy * u * u);
+            }
+            yfac[fc][ty] = v;
+        }
 
-        // centred x coordinates of this lane's nodes (clamped for the ragged tail)
+        // centred x coordinates of this lane's nodes (clamped for the ragged
+        // tail), for the tiles that form the x terms in registers
         float uxc[TXW];
 #pragma unroll
         for (int i = 0; i < TXW; ++i) {
             const int x = 16 * (w + NW * i) + xr;
-            uxc[i] = (float)(node_pos(box[0], x < p.nx ? x : p.nx - 1, hx) - cx);
+            uxc[i] = ATAB ? 0.f : (float)(node_pos(box[0], x < p.nx ? x : p.nx - 1, hx) - cx);
         }
         float tn[TXW][TY], tX[TXW][TY], in_[TXW][TY], iX[TXW][TY];
 #pragma unroll
@@ -253,28 +288,44 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                 const int j = tid % NY, sj = tid / NY;
                 if (sj < kPass) {
                     const float uyc = (float)(node_pos(box[2], j < p.ny ? j : p.ny - 1, hy) - cy);
+                    const float uxc = ATAB ? (float)(node_pos(box[0], j < p.nx ? j : p.nx - 1, hx) - cx) : 0.f;
                     for (int s = sj; s < cn; s += kPass) {
-                        const float d = uyc - sF[c0 + s].uy;
-                        stage.b[s][j] = (sF[c0 + s].nk * d) * d;
+                        const CoefF c = sF[c0 + s];
+                        const float d = uyc - c.uy;
+                        stage.t.b[s][j] = (c.nk * d) * d;
+                        if constexpr (ATAB) {
+                            const float dx = uxc - c.ux, t = c.nk * dx;
+                            float2_t v;
+                            v[0] = fmaf(t, dx, c.a);
+                            v[1] = fmaf(t, dx, c.al);
+                            stage.t.ai[s][j] = v;
+                        }
                     }
                 }
             }
             __syncthreads();
             int s = 0;
             for (; s + 1 < cn; s += 2) {
-                const CoefF c1 = sF[c0 + s], c2 = sF[c0 + s + 1];
                 float A1[TXW], I1[TXW], A2[TXW], I2[TXW];
 #pragma unroll
                 for (int i = 0; i < TXW; ++i) {
-                    const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
-                    const float d2 = uxc[i] - c2.ux, t2 = c2.nk * d2;
-                    A1[i] = fmaf(t1, d1, c1.a); I1[i] = fmaf(t1, d1, c1.al);
-                    A2[i] = fmaf(t2, d2, c2.a); I2[i] = fmaf(t2, d2, c2.al);
+                    if constexpr (ATAB) {
+                        const float2_t v1 = stage.t.ai[s][16 * (w + NW * i) + xr];
+                        const float2_t v2 = stage.t.ai[s + 1][16 * (w + NW * i) + xr];
+                        A1[i] = v1[0]; I1[i] = v1[1];
+                        A2[i] = v2[0]; I2[i] = v2[1];
+                    } else {
+                        const CoefF c1 = sF[c0 + s], c2 = sF[c0 + s + 1];
+                        const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
+                        const float d2 = uxc[i] - c2.ux, t2 = c2.nk * d2;
+                        A1[i] = fmaf(t1, d1, c1.a); I1[i] = fmaf(t1, d1, c1.al);
+                        A2[i] = fmaf(t2, d2, c2.a); I2[i] = fmaf(t2, d2, c2.al);
+                    }
                 }
 #pragma unroll
                 for (int k = 0; k < KS; ++k) {
-                    const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.b[s][16 * k + 4 * g]);
-                    const float4_t b2 = *reinterpret_cast<const float4_t*>(&stage.b[s + 1][16 * k + 4 * g]);
+                    const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.t.b[s][16 * k + 4 * g]);
+                    const float4_t b2 = *reinterpret_cast<const float4_t*>(&stage.t.b[s + 1][16 * k + 4 * g]);
 #pragma unroll
                     for (int i = 0; i < TXW; ++i)
 #pragma unroll
@@ -290,14 +341,20 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
                 }
             }
             if (s < cn) {
-                const CoefF c1 = sF[c0 + s];
 #pragma unroll
                 for (int i = 0; i < TXW; ++i) {
-                    const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
-                    const float A1 = fmaf(t1, d1, c1.a), I1 = fmaf(t1, d1, c1.al);
+                    float A1, I1;
+                    if constexpr (ATAB) {
+                        const float2_t v1 = stage.t.ai[s][16 * (w + NW * i) + xr];
+                        A1 = v1[0]; I1 = v1[1];
+                    } else {
+                        const CoefF c1 = sF[c0 + s];
+                        const float d1 = uxc[i] - c1.ux, t1 = c1.nk * d1;
+                        A1 = fmaf(t1, d1, c1.a); I1 = fmaf(t1, d1, c1.al);
+                    }
 #pragma unroll
                     for (int k = 0; k < KS; ++k) {
-                        const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.b[s][16 * k + 4 * g]);
+                        const float4_t b1 = *reinterpret_cast<const float4_t*>(&stage.t.b[s][16 * k + 4 * g]);
 #pragma unroll
                         for (int m = 0; m < 4; ++m) {
                             const int j = 4 * k + m;
@@ -362,18 +419,15 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             for (int i = 0; i < TXW; ++i) {
                 // y stage on the VALU (FP32), then the x stage in FP64
                 float H[2][4] = {{0, 0, 0, 0}, {0, 0, 0, 0}}, HI[2] = {0, 0};
+                float4_t Y[4];
 #pragma unroll
                 for (int j = 0; j < TY; ++j) {
-                    const int ty = 16 * (j / 4) + 4 * eg + (j % 4);
-                    float y0 = 0.f, y1 = 0.f, y2 = 0.f, y3 = 0.f;
-                    if (ty < p.ny) {
-                        const double u = node_pos(ebox[2], ty, ehy);
-                        const double a0 = ehy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
-                        y0 = (float)a0;
-                        y1 = (float)(u < 0.0 ? a0 * u : 0.0);
-                        y2 = (float)(u < 0.0 ? 0.0 : a0 * u);
-                        y3 = (float)(a0 * u * u);
+                    if (j % 4 == 0) {
+#pragma unroll
+                        for (int fc = 0; fc < 4; ++fc)
+                            Y[fc] = *reinterpret_cast<const float4_t*>(&yfac[fc][16 * (j / 4) + 4 * eg]);
                     }
+                    const float y0 = Y[0][j % 4], y1 = Y[1][j % 4], y2 = Y[2][j % 4], y3 = Y[3][j % 4];
                     const float fa = __builtin_amdgcn_exp2f(tn[i][j] * kLog2e);
                     const float fb = __builtin_amdgcn_exp2f(tX[i][j] * kLog2e);
                     H[0][0] = fmaf(fa, y0, H[0][0]); H[0][1] = fmaf(fa, y1, H[0][1]);
@@ -405,23 +459,27 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
             const double yscale = (exr < 4 && bound > 0.0) ? ldexp(1.0, -ilogb(bound)) : 1.0;
             const double unscale =
                 (CT == KBL_PREC_MIXED_FP16 ? 1.0 / ((double)kF16Scale * kF16Scale) : 1.0) / yscale;
+            // this lane's factor (zero in the unused columns), times the
+            // column's power of two
+            const float ysf = exr < 4 ? (float)yscale : 0.f;
             float yb[TY];
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                const int ty = 16 * (j / 4) + 4 * eg + (j % 4);
-                double v = 0.0;
-                if (ty < p.ny && exr < 4) {
-                    const double u = node_pos(ebox[2], ty, ehy);
-                    const double wy = ehy * ((ty == 0 || ty == p.ny - 1) ? 0.5 : 1.0);
-                    v = exr == 0 ? wy
-                      : exr == 1 ? (u < 0.0 ? wy * u : 0.0)
-                      : exr == 2 ? (u < 0.0 ? 0.0 : wy * u)
-                                : wy * u * u;
-                }
-                yb[j] = (float)(v * yscale);
+            for (int k = 0; k < KS; ++k) {
+                const float4_t y4 = *reinterpret_cast<const float4_t*>(&yfac[exr & 3][16 * k + 4 * eg]);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) yb[4 * k + i] = y4[i] * ysf;
             }
             YSplit<KS, CT> ysp;
             split_y<KS, CT>(yb, ysp);
+            // x stage without branches on the lane's column: every lane sums
+            // X.{w, m, p, q} times its C entries of each T envelope and X.w
+            // times those of each I envelope; which partials these are
+            // depends only on the column (exr) and is settled after the
+            // tiles.  The sums are the products of the per-entry form in
+            // the same order, and the column's unscale (a power of two) is
+            // exact at either place.
+            const float fsh = CT == KBL_PREC_MIXED_FP16 ? kF16Log2Scale : 0.f;
+            double sT[2][4] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}}, sI[2] = {0.0, 0.0};
 #pragma unroll
             for (int i = 0; i < TXW; ++i) {
                 // x rows of the C result held by this lane
@@ -431,36 +489,39 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
 #pragma unroll
                 for (int env = 0; env < 4; ++env) {
                     float f[TY];
+                    const float sh = fsh - nsh[env];
 #pragma unroll
                     for (int j = 0; j < TY; ++j) {
                         const float q = env == 0 ? tn[i][j] : env == 1 ? tX[i][j] : env == 2 ? in_[i][j] : iX[i][j];
-                        f[j] = __builtin_amdgcn_exp2f(fmaf(q, kLog2e, -nsh[env]));
+                        f[j] = __builtin_amdgcn_exp2f(fmaf(q, kLog2e, sh));
                     }
                     const float4_t c = mfma_ystage<KS, CT>(f, ysp);
                     __builtin_amdgcn_sched_barrier(0);
-                    if (exr < 4) {
 #pragma unroll
-                        for (int r = 0; r < 4; ++r) {
-                            const double h = c[r] * unscale;
-                            if (env < 2) {
-                                double* pv = part + 6 * env;
-                                if (exr == 0) {
-                                    pv[0] += X[r].w * h; pv[1] += X[r].m * h; pv[2] += X[r].p * h;
-                                    pv[5] += 0.5 * X[r].q * h;
-                                } else if (exr == 1) {
-                                    pv[3] += X[r].w * h;
-                                } else if (exr == 2) {
-                                    pv[4] += X[r].w * h;
-                                } else {
-                                    pv[5] += 0.5 * X[r].w * h;
-                                }
-                            } else if (exr == 0) {
-                                part[12 + env - 2] += X[r].w * h;
-                            }
+                    for (int r = 0; r < 4; ++r) {
+                        const double h = c[r];
+                        if (env < 2) {
+                            sT[env][0] += X[r].w * h; sT[env][1] += X[r].m * h;
+                            sT[env][2] += X[r].p * h; sT[env][3] += X[r].q * h;
+                        } else {
+                            sI[env - 2] += X[r].w * h;
                         }
                     }
                 }
             }
+            const double u0 = exr == 0 ? unscale : 0.0, u1 = exr == 1 ? unscale : 0.0;
+            const double u2 = exr == 2 ? unscale : 0.0, u3 = exr == 3 ? unscale : 0.0;
+#pragma unroll
+            for (int v = 0; v < 2; ++v) {
+                part[6 * v + 0] = u0 * sT[v][0];
+                part[6 * v + 1] = u0 * sT[v][1];
+                part[6 * v + 2] = u0 * sT[v][2];
+                part[6 * v + 3] = u1 * sT[v][0];
+                part[6 * v + 4] = u2 * sT[v][0];
+                part[6 * v + 5] = 0.5 * (u0 * sT[v][3] + u3 * sT[v][0]);
+            }
+            part[12] = u0 * sI[0];
+            part[13] = u0 * sI[1];
         }
         if (CT != KBL_PREC_MIXED_FP32) {
             // back to the element's log-peak scale (exact powers of two)
@@ -525,15 +586,15 @@ bool mixed_tile_fits(int t, int nx, int ny) {
     return nx <= 16 * m.txw * m.nw && ny <= 16 * m.ks;
 }
 
-// Defaults from a measured sweep (48x48: FP32 VALU contraction prefers three
-// single-tile waves, the MFMA contraction one wave of three tiles; 64x64:
-// two waves of two tiles).
+// Defaults from a measured sweep (48x48: three single-tile waves for every
+// contraction; 64x64: the FP16 MFMA contraction two waves of two tiles, the
+// FP32 VALU and BF16 MFMA contractions four single-tile waves).
 int default_mixed_tile(int nx, int ny, int precision) {
     const int n = nx > ny ? nx : ny;
     if (n <= 16) return 0;
     if (n <= 32) return 1;
-    if (n <= 48) return precision == KBL_PREC_MIXED_FP32 ? 4 : 3;
-    return 5;
+    if (n <= 48) return 4;
+    return precision == KBL_PREC_MIXED_FP16 ? 5 : 6;
 }
 
 }  // namespace
