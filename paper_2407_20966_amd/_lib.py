@@ -34,7 +34,7 @@ FP64_TILES = {0: (16, 16, 1, 1, 0), 1: (16, 16, 2, 2, 0), 2: (16, 16, 3, 3, 0),
               3: (16, 16, 3, 3, 1), 4: (16, 8, 3, 6, 0), 5: (16, 16, 4, 4, 0),
               6: (16, 16, 4, 4, 1), 7: (32, 8, 2, 8, 1), 8: (16, 16, 2, 4, 0),
               9: (16, 16, 4, 2, 0), 10: (16, 16, 2, 2, 2), 11: (16, 16, 3, 3, 2),
-              12: (16, 16, 4, 4, 2), 13: (16, 8, 3, 6, 2), 14: (32, 16, 2, 4, 2)}
+              12: (16, 16, 4, 4, 2), 13: (16, 8, 3, 6, 2)}
 # d = 3 tiles: (BX, BY, BZ, TX, TY, TZ) covers nx <= BX TX, ny <= BY TY, any nz
 FP64_TILES_3D = {0: (8, 8, 4, 2, 2, 2), 1: (8, 8, 4, 3, 3, 1), 2: (16, 16, 1, 2, 2, 2),
                  3: (16, 16, 1, 3, 3, 1), 4: (16, 16, 1, 4, 4, 1), 5: (8, 8, 4, 2, 2, 4),

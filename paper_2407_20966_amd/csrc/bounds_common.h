@@ -143,10 +143,9 @@ __device__ __forceinline__ int wave_min_i32(int v) {
                min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
 
-// Shared scratch for the per-element prologue and epilogue (up to 8 waves:
-// the eight-wave 2D FP64 tile; every other kernel has at most 4).
+// Shared scratch for the per-element prologue and epilogue (up to 4 waves).
 struct Red {
-    double v[2 * kWaves][16];
+    double v[kWaves][16];
     uint32_t flags;
 };
 

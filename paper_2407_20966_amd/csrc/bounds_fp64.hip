@@ -38,12 +38,12 @@ namespace {
 // traffic and barriers).
 template <int BX, int BY, int TX, int TY, int BTAB>
 __global__ __launch_bounds__(BX * BY)
-__attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (BX * BY > kThreads ? 4 : TX * TY <= 9 ? 3 : 2) : 1))) void bounds_fp64_2d(BoundsArgs p) {
+__attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) void bounds_fp64_2d(BoundsArgs p) {
     constexpr int NT = BX * BY;
     constexpr int NXM = BX * TX;
     constexpr int NYM = BY * TY;
     constexpr int kTabStates = 32;
-    static_assert(NT % 64 == 0 && NT <= 2 * kThreads, "workgroup must be 1-8 waves");
+    static_assert(NT % 64 == 0 && NT <= kThreads, "workgroup must be 1-4 waves");
     static_assert(BTAB == 0 || (NXM == NYM && NYM <= NT), "table tiles are square");
     __shared__ Coef sC[kMaxStates];
     __shared__ double sB[BTAB ? kTabStates : 1][BTAB ? NYM : 1];
@@ -636,9 +636,6 @@ constexpr Tile2D kTiles2D[] = {
     KBL_TILE(16, 16, 3, 3, 2),   // 11: n <= 48, A and B from LDS
     KBL_TILE(16, 16, 4, 4, 2),   // 12: n <= 64, A and B from LDS
     KBL_TILE(16, 8, 3, 6, 2),    // 13: n <= 48, two waves, A and B from LDS
-    // 14: n <= 64, eight waves of 2 x 4 nodes per thread (128 VGPRs): two
-    // workgroups, four waves per SIMD, where the 4 x 4 tile holds two
-    KBL_TILE(32, 16, 2, 4, 2),
 };
 #undef KBL_TILE
 constexpr int kNumTiles2D = sizeof(kTiles2D) / sizeof(kTiles2D[0]);
