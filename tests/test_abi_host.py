@@ -304,6 +304,7 @@ def test_python_tile_tables_match_the_kernels():
     # returned by kbl_autotune_bounds are positions in these tables
     assert _tile_table("bounds_fp64.hip", "KBL_TILE") == L.FP64_TILES
     assert _tile_table("bounds_fp64_3d.hip", "KBL_TILE3") == L.FP64_TILES_3D
+    assert _tile_table("bounds_mixed.hip", "KBL_MTILE") == L.MIXED_TILES
 
 
 # ---------------------------------------------------------------- 1D FR solver

@@ -82,6 +82,24 @@ def test_mixed_small_stencil_box(kbl, prec, n):
     check(kbl, wl, prec)
 
 
+# every mixed tile configuration (forced through the tuning knob) in every
+# form, each on a ragged grid that leaves some of its lanes' nodes outside
+from paper_2407_20966_amd._lib import MIXED_TILES  # noqa: E402
+
+MIXED_TILE_EXTENTS = {t: (16 * txw * nw, 16 * ks) for t, (txw, ks, nw) in MIXED_TILES.items()}
+
+
+@pytest.mark.parametrize("prec", list(PRECS))
+@pytest.mark.parametrize("tile", sorted(MIXED_TILE_EXTENTS))
+def test_every_mixed_tile(kbl, monkeypatch, tile, prec):
+    mx, my = MIXED_TILE_EXTENTS[tile]
+    n = (mx - 3, my - 2)
+    wl = synth.make_quad_workload(N=6, seed=400 + tile, grid_nodes=n[0], name=f"mq_tile{tile}")
+    wl.grid = GridSpec(GRID_STENCIL, n, k=4.0)
+    monkeypatch.setenv("KBL_MIXED_TILE", str(tile))
+    check(kbl, wl, prec)
+
+
 @pytest.mark.parametrize("prec", list(PRECS))
 def test_mixed_global_box(kbl, prec):
     wl = synth.make_quad_workload(N=12, seed=78, field_kind="sine", grid_nodes=64,
