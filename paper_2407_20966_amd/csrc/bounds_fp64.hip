@@ -134,6 +134,51 @@ __attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) voi
                     }
                     __syncthreads();
                 }
+                if constexpr (BTAB == 2 && TX * TY > 9) {
+                    // Software-pipelined: the table values of state s + 1 are
+                    // read before the pair work of state s, so the LDS latency
+                    // is covered by that work within the wave (tiles at two
+                    // waves per SIMD: tri2m 159.4 -> 155.5 ms; the three-wave
+                    // tiles hide it across waves and measured slower with
+                    // it).  The last iteration re-reads its own state (in
+                    // range, unused).
+                    double ca[TX], cai[TX], cb[TY];
+#pragma unroll
+                    for (int i = 0; i < TX; ++i) {
+                        ca[i] = sA[0][tx + BX * i];
+                        cai[i] = sA[1][tx + BX * i];
+                    }
+#pragma unroll
+                    for (int j = 0; j < TY; ++j) cb[j] = sB[0][ty + BY * j];
+#pragma unroll 2
+                    for (int s = 0; s < tn; ++s) {
+                        const int sn = s + 1 < tn ? s + 1 : s;
+                        double na[TX], nai[TX], nb[TY];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) {
+                            na[i] = sA[2 * sn][tx + BX * i];
+                            nai[i] = sA[2 * sn + 1][tx + BX * i];
+                        }
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) nb[j] = sB[sn][ty + BY * j];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i)
+#pragma unroll
+                            for (int j = 0; j < TY; ++j) {
+                                const double q = ca[i] + cb[j];
+                                const double qi = cai[i] + cb[j];
+                                qtn[i][j] = fmin(qtn[i][j], q);
+                                qtx[i][j] = fmax(qtx[i][j], q);
+                                qin[i][j] = fmin(qin[i][j], qi);
+                                qix[i][j] = fmax(qix[i][j], qi);
+                            }
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) { ca[i] = na[i]; cai[i] = nai[i]; }
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) cb[j] = nb[j];
+                    }
+                    continue;
+                }
 #pragma unroll 2
                 for (int s = 0; s < tn; ++s) {
                     double a[TX], ai[TX], b[TY];
