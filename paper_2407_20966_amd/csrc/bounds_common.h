@@ -228,6 +228,33 @@ __device__ __forceinline__ double exp_tab(double x, const ExpPair* tab) {
     return ldexp(fma(T.t24, q, T.t), ni >> 8);
 }
 
+// exp_tab in two parts, the same operations in the same order: the index
+// and the polynomial of the reduced argument, then the table product.  A
+// caller can issue the table reads of several values together between the
+// two parts.
+struct ExpPrep {
+    double q;
+    int ni;
+};
+__device__ __forceinline__ ExpPrep exp_prep(double x) {
+    constexpr double kInvStep = 0x1.71547652b82fep+8;   // 256 / ln 2
+    x = fmax(x, -1100.0);
+    const double t = fma(x, kInvStep, 0x1.8p52);
+    const double n = t - 0x1.8p52;
+    ExpPrep e;
+    e.ni = __double2loint(t);
+    double r = fma(-n, kLn2By256Hi, x);
+    r = fma(-n, kLn2By256Lo, r);
+    double q = r + 4.0;
+    q = fma(r, q, 12.0);
+    q = fma(r, q, 24.0);
+    e.q = r * q;
+    return e;
+}
+__device__ __forceinline__ double exp_fin(const ExpPrep& e, const ExpPair& T) {
+    return ldexp(fma(T.t24, e.q, T.t), e.ni >> 8);
+}
+
 // Copies the exp table into LDS; the caller's next barrier publishes it.
 template <int NT>
 __device__ __forceinline__ void stage_exp_table(ExpPair* tab) {
