@@ -88,22 +88,16 @@ __attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) voi
             uy[j] = node_pos(loy, jj < p.ny ? jj : p.ny - 1, hy);
         }
 
+        // No +-inf starting values (two moves per accumulator): the
+        // stencil's first state writes the envelopes in the peeled first
+        // step of the hot loop; the empty asm gives the registers a defined
+        // value until then.
         double qtn[TX][TY], qtx[TX][TY], qin[TX][TY], qix[TX][TY];
-        constexpr bool PIPE = BTAB == 2 && TX * TY > 9;
 #pragma unroll
         for (int i = 0; i < TX; ++i)
 #pragma unroll
-            for (int j = 0; j < TY; ++j) {
-                if constexpr (PIPE) {
-                    // no +-inf starting values (two moves per accumulator):
-                    // the stencil's first state writes the envelopes in the
-                    // peeled step of the hot loop; the empty asm gives the
-                    // registers a defined value until then
-                    asm volatile("" : "=v"(qtn[i][j]), "=v"(qtx[i][j]), "=v"(qin[i][j]), "=v"(qix[i][j]));
-                } else {
-                    qtn[i][j] = kInf; qtx[i][j] = -kInf; qin[i][j] = kInf; qix[i][j] = -kInf;
-                }
-            }
+            for (int j = 0; j < TY; ++j)
+                asm volatile("" : "=v"(qtn[i][j]), "=v"(qtx[i][j]), "=v"(qin[i][j]), "=v"(qix[i][j]));
 
         for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
             const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
@@ -222,9 +216,9 @@ __attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) voi
                     }
                     continue;
                 }
-#pragma unroll 2
-                for (int s = 0; s < tn; ++s) {
-                    double a[TX], ai[TX], b[TY];
+                // the x terms a, a + l and the y terms b of state s at this
+                // thread's nodes, from the tables or from the coefficients
+                auto terms = [&](int s, double* a, double* ai, double* b) {
                     if (BTAB == 2) {
 #pragma unroll
                         for (int i = 0; i < TX; ++i) {
@@ -252,6 +246,29 @@ __attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) voi
                             b[j] = (c.nk * d) * d;
                         }
                     }
+                };
+                int s0 = 0;
+                if (c0 == 0 && t0 == 0) {
+                    // the stencil's first state sets the envelopes
+                    double a[TX], ai[TX], b[TY];
+                    terms(0, a, ai, b);
+#pragma unroll
+                    for (int i = 0; i < TX; ++i)
+#pragma unroll
+                        for (int j = 0; j < TY; ++j) {
+                            const double q = a[i] + b[j];
+                            const double qi = ai[i] + b[j];
+                            qtn[i][j] = q;
+                            qtx[i][j] = q;
+                            qin[i][j] = qi;
+                            qix[i][j] = qi;
+                        }
+                    s0 = 1;
+                }
+#pragma unroll 2
+                for (int s = s0; s < tn; ++s) {
+                    double a[TX], ai[TX], b[TY];
+                    terms(s, a, ai, b);
 #pragma unroll
                     for (int i = 0; i < TX; ++i)
 #pragma unroll
