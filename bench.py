@@ -142,7 +142,8 @@ def _counter_per_dispatch(csv_path: str, counter: str):
 def write_traffic(workload: str, fetch_csv: str, write_csv: str) -> dict:
     """Turns a FETCH_SIZE run and a WRITE_SIZE run of bench.py (each with
     --copy-calibration) into an entry of the traffic file, replacing an entry
-    of the same workload, kernel and grid.  Calibration: the device copy reads
+    of the same workload, kernel and grid and the workload's entries of older
+    sources.  Calibration: the device copy reads
     as many bytes as it writes, and WRITE_SIZE counts the bytes written, so
     FETCH_SIZE is scaled by WRITE/FETCH of the copy.  The profiled launch is
     the kernel and grid of the last FP64 bounds dispatch (the timed launches;
@@ -194,8 +195,10 @@ def write_traffic(workload: str, fetch_csv: str, write_csv: str) -> dict:
     keep = []
     for b in blocks:
         kv = dict(l.strip().split(" = ", 1) for l in b if " = " in l)
-        if (kv.get("workload"), kv.get("kernel"), kv.get("grid_threads")) != \
-                (workload, kname, str(grid)):
+        same = (kv.get("workload"), kv.get("kernel"), kv.get("grid_threads")) == \
+            (workload, kname, str(grid))
+        stale = kv.get("workload") == workload and kv.get("source_sha256") != entry["source_sha256"]
+        if not (same or stale):   # counters of older sources are never used again
             keep.append(b)
     with open(path, "w") as fh:
         fh.writelines(head)
@@ -243,8 +246,7 @@ def kernel_shape(kbl, dim, tuned, n_elem, n_cu):
     autotuned choice (None, None without one)."""
     if dim == 1 or not tuned:
         return ("bounds_fp64_1d" if dim == 1 else f"bounds_fp64_{dim}d"), None
-    wpc = tuned["workgroups_per_cu"]
-    blocks = n_elem if wpc == 0 else min(n_elem, wpc * n_cu)
+    blocks = kbl._lib.launch_workgroups(tuned, n_elem, n_cu)
     if dim == 2:
         bx, by, tx, ty, md = kbl._lib.FP64_TILES[tuned["tile"]]
         return f"bounds_fp64_2d<{bx}, {by}, {tx}, {ty}, {md}>", blocks * bx * by
@@ -446,7 +448,7 @@ def time_3d(args, kbl, torch, synth, stream):
     tuned = None
     if not args.no_autotune:
         c = kbl.autotune_bounds(st, rp, cl, wl.n_s, vg, prm, sample_elems=8192, stream=stream)
-        tuned = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
+        tuned = kbl._lib.decode_autotune(c)
         print(f"[bench] autotuned hex32: {tuned}", file=sys.stderr, flush=True)
     steps = max(2, args.steps // 2)
     ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
@@ -591,7 +593,7 @@ def autotune(args, kbl, d, prm, stream, label, sample=65536):
     wl = d.wl
     c = kbl.autotune_bounds(d.st, d.rp, d.cl, wl.n_s, d.vg, prm, sample_elems=sample,
                             stream=stream)
-    t = {"tile": c // 8, "workgroups_per_cu": [0, 1, 2, 4, 8][c % 8]}
+    t = kbl._lib.decode_autotune(c)
     print(f"[bench] autotuned {label}: {t}", file=sys.stderr, flush=True)
     return t
 
@@ -848,7 +850,8 @@ def main(argv=None):
     cfg.update({"precision": "fp64", "parity_tol": 1e-12})
     if head["launch"]:
         cfg["launch"] = {"autotuned": head["launch"],
-                         "note": "workgroups_per_cu 0 = one workgroup per element"}
+                         "note": "elements_per_workgroup: elements computed by one "
+                                 "workgroup; workgroups_per_cu: persistent grid"}
     out = {"metric": METRIC, "value": head["value"], "unit": "elements/s",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": head["ms_per_step"], "higher_is_better": True, "scaling": "weak",

@@ -171,13 +171,17 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
  *                              velocity grid)
  *   KBL_MIXED_TILE=<t>         mixed-precision tile configuration index
  *   KBL_PERSISTENT_BLOCKS=<g>  grid of g workgroups walking the elements
- *                              (0 = one workgroup per element)
+ *                              (0 = one workgroup per element, -k = k
+ *                              elements per workgroup)
+ * Without either, a 2D launch has each workgroup compute two elements (half
+ * as many workgroups as elements; reading (A): one workgroup per element),
+ * a 1D or 3D launch one workgroup per element.
  */
 /*
  * kbl_autotune_bounds - picks the launch configuration of kbl_compute_bounds
  * for this problem shape by timing every candidate on the caller's inputs:
- * each tile configuration that fits the velocity grid, launched either with
- * one workgroup per element or as a persistent grid of 1, 2, 4 or 8
+ * each tile configuration that fits the velocity grid, launched with one,
+ * two or four elements per workgroup or as a persistent grid of 1, 2, 4 or 8
  * workgroups per compute unit (each workgroup then walks elements in a grid
  * stride).  Timing uses the first `sample_elems` elements (all when <= 0);
  * each candidate keeps the better of two trials, and the default launch is
@@ -188,7 +192,8 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
  * (and the status in `elem_status` when non-null).  Returns 8 * tile + shape
  * for the chosen candidate (tile: index of the tile configuration, 0 in 1D;
  * shape: 0 = one workgroup per element, 1..4 = 1, 2, 4, 8 workgroups per
- * compute unit), or -1 on bad arguments or a HIP failure.
+ * compute unit, 5 = two and 6 = four elements per workgroup), or -1 on bad
+ * arguments or a HIP failure.
  */
 int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_elem, int32_t n_s,
                             int64_t nnz, const double* states, const int32_t* rowptr,

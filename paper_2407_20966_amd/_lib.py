@@ -41,6 +41,28 @@ FP64_TILES_3D = {0: (8, 8, 4, 2, 2, 2), 1: (8, 8, 4, 3, 3, 1), 2: (16, 16, 1, 2,
                  6: (8, 8, 4, 3, 3, 2), 7: (8, 8, 4, 4, 4, 1), 8: (16, 16, 1, 3, 3, 2)}
 MIXED_TILES = {0: (1, 1, 1), 1: (2, 2, 1), 2: (1, 2, 2), 3: (3, 3, 1), 4: (1, 3, 3),
                5: (2, 4, 2), 6: (1, 4, 4)}
+# launch shapes of kbl_autotune_bounds' result (8 * tile + shape)
+AUTOTUNE_SHAPES = ({"elements_per_workgroup": 1}, {"workgroups_per_cu": 1},
+                   {"workgroups_per_cu": 2}, {"workgroups_per_cu": 4},
+                   {"workgroups_per_cu": 8}, {"elements_per_workgroup": 2},
+                   {"elements_per_workgroup": 4})
+
+
+def decode_autotune(c: int) -> dict:
+    """Tile index and launch shape of a kbl_autotune_bounds result."""
+    return {"tile": c // 8, **AUTOTUNE_SHAPES[c % 8]}
+
+
+def launch_workgroups(shape: dict, n_elem: int, n_cu: int) -> int:
+    """Workgroups of a launch shape (as decode_autotune gives it) for n_elem elements."""
+    if "workgroups_per_cu" in shape:
+        return min(n_elem, shape["workgroups_per_cu"] * n_cu)
+    k = min(shape["elements_per_workgroup"], n_elem)
+    if k <= 1:
+        return n_elem
+    return 8 * (((n_elem + 7) // 8 + k - 1) // k)   # k consecutive elements per workgroup
+
+
 RS_BAD_INPUT = 1 << 16
 FLAG_INDEPENDENT_ALPHA = 0x1
 FLAG_ENERGY_PERSTATE = 0x2

@@ -153,13 +153,19 @@ struct Red {
 // XCDs (8 on MI355X, each with its own L2), so workgroup b runs on XCD b % 8.
 // Each XCD is given a contiguous range of elements, walked by its workgroups
 // in a grid stride: stencil neighbours (nearby element ids on structured and
-// locally numbered meshes) are then read through the same L2.  Every element
-// is visited exactly once for any grid size >= 1.
+// locally numbered meshes) are then read through the same L2.  With
+// grid_blocks = -k (k elements per workgroup) workgroup j of an XCD takes
+// the k consecutive elements from j k on instead, so that the elements in
+// flight on an XCD stay one contiguous band (a grid stride would put its
+// two or four passes half or a quarter of the range apart); the host sizes
+// that grid so that the chunks cover every XCD's range, else the grid
+// stride is kept.  Every element is visited exactly once for any grid size
+// >= 1.
 constexpr int kXcds = 8;
 struct ElemRange {
     int64_t e, end, step;
 };
-__device__ __forceinline__ ElemRange xcd_range(int64_t n) {
+__device__ __forceinline__ ElemRange xcd_range(int64_t n, int64_t grid_blocks) {
     static_assert(kXcds == 8, "shifts below assume 8 XCDs");
     const int64_t G = gridDim.x, b = blockIdx.x;
     if (G >= kXcds) {
@@ -171,6 +177,13 @@ __device__ __forceinline__ ElemRange xcd_range(int64_t n) {
         const int64_t q = n >> 3, r = n & (kXcds - 1);
         const int64_t start = x * q + (x < r ? x : r);
         const int64_t cnt = q + (x < r ? 1 : 0);
+        if (grid_blocks < 0) {
+            const int64_t k = grid_blocks < -n ? n : -grid_blocks;
+            if (gx * k >= cnt) {
+                const int64_t e0 = start + j * k;
+                return ElemRange{e0, e0 + k < start + cnt ? e0 + k : start + cnt, 1};
+            }
+        }
         return ElemRange{start + j, start + cnt, gx};
     }
     // fewer workgroups than XCDs: one group per workgroup

@@ -57,7 +57,7 @@ __attribute__((amdgpu_waves_per_eu(BTAB == 2 ? (TX * TY <= 9 ? 3 : 2) : 1))) voi
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(BX * BY) void bounds_fp64_2d_energy(BoundsArgs p) {
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
@@ -598,7 +598,7 @@ __global__ __launch_bounds__(NT) void bounds_fp64_1d_energy(BoundsArgs p) {
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     stage_exp_table<NT>(sExp);   // published by the prologue's barriers
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {
@@ -676,7 +676,7 @@ void bounds_fp64_1d(BoundsArgs p) {
     const int tid = threadIdx.x;
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     stage_exp_table<NT>(sExp);   // published by the prologue's barriers
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {

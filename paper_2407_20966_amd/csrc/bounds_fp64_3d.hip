@@ -54,7 +54,7 @@ void bounds_fp64_3d(BoundsArgs p) {
     const double rm = 1.0 - p.r_fac, rp = 1.0 + p.r_fac;
     stage_exp_table<NT>(sExp);   // published by the prologue's barriers
 
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {

@@ -209,7 +209,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KBL_MIX
     const int tid = threadIdx.x;
     const int w = tid >> 6, l = tid & 63, xr = l & 15, g = l >> 4;
 
-    for (ElemRange er = xcd_range(p.n_elem); er.e < er.end; er.e += er.step) {
+    for (ElemRange er = xcd_range(p.n_elem, p.grid_blocks); er.e < er.end; er.e += er.step) {
         const int64_t e = er.e;
         const int64_t row0 = p.rowptr[e], row1 = p.rowptr[e + 1];
         if (row0 < 0 || row1 <= row0 || row1 > p.nnz) {

@@ -32,12 +32,21 @@ struct BoundsArgs {
     double r_fac;
     double rho_floor;
     int64_t grid_blocks;  // host launch shape: 0 = one workgroup per element,
-                          // > 0 = persistent grid of that many workgroups
+                          // > 0 = persistent grid of that many workgroups,
+                          // < 0 = -grid_blocks elements per workgroup
 };
 
 // Workgroups to launch for n_elem elements under a BoundsArgs::grid_blocks choice.
 inline unsigned bounds_grid(const BoundsArgs& a) {
-    int64_t g = a.grid_blocks > 0 && a.grid_blocks < a.n_elem ? a.grid_blocks : a.n_elem;
+    int64_t g = a.n_elem;
+    if (a.grid_blocks > 0 && a.grid_blocks < a.n_elem) g = a.grid_blocks;
+    if (a.grid_blocks < 0 && a.n_elem > 0) {
+        // -grid_blocks consecutive elements per workgroup (at most n_elem):
+        // a multiple of 8 workgroups, ceil(ceil(n_elem / 8) / k) per XCD, so
+        // that every XCD's chunks cover its range (see xcd_range)
+        const int64_t k = a.grid_blocks < -a.n_elem ? a.n_elem : -a.grid_blocks;
+        g = 8 * (((a.n_elem + 7) / 8 + k - 1) / k);
+    }
     if (g > (int64_t)INT32_MAX) g = INT32_MAX;
     return (unsigned)g;
 }

@@ -1,8 +1,9 @@
 """Launch configurations of the bounds kernels: persistent grids and autotuning.
 
-A persistent launch (fewer workgroups than elements, each walking elements
-in a grid stride) must give bit-identical results to one workgroup per
-element with the same tile; the autotuned choice must stay within the FP64
+Every launch shape (one workgroup per element, several elements per
+workgroup, persistent grids walking the elements in a grid stride) must give
+bit-identical results to the default launch with the same tile; the
+autotuned choice must stay within the FP64
 parity tolerance of the oracle (and, for the mixed forms, within the mixed
 tolerance), on uneven triangle stencils and on quads.
 """
@@ -43,7 +44,7 @@ def bounds(kbl, wl, precision=0):
     return b.cpu().numpy(), s.cpu().numpy()
 
 
-@pytest.mark.parametrize("blocks", [1, 7, 300])
+@pytest.mark.parametrize("blocks", [1, 7, 300, 0, -3, -64, -100000])
 @pytest.mark.parametrize("case", ["tri", "quad", "line"])
 def test_persistent_grid_is_bit_identical(kbl, monkeypatch, case, blocks):
     if case == "tri":
