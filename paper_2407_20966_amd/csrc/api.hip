@@ -294,8 +294,7 @@ int32_t kbl_autotune_bounds(const kbl_params* params, int32_t dim, int64_t n_ele
         return -1;
     if (n_elem == 0 || !bounds) return -1;
     hipStream_t st = (hipStream_t)stream;
-    // candidates: every tile that fits the grid x {one workgroup per element,
-    // persistent grids of 1, 2, 4, 8 workgroups per CU}
+    // candidates: every tile that fits the grid x the launch shapes below
     std::vector<int> tiles;
     if (dim >= 2) {
         const int nt = dim == 3 ? kbl::bounds_tile_count_3d()
