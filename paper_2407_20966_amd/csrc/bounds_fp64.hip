@@ -692,17 +692,35 @@ void bounds_fp64_1d(BoundsArgs p) {
         }
         const double lo = box[0];
         const double h = (box[1] - box[0]) / (double)(p.nx - 1);
+        // no +-inf starting values: the stencil's first state sets the
+        // envelopes (the empty asm gives the registers a defined value)
         double u[T], qtn[T], qtx[T], qin[T], qix[T];
 #pragma unroll
         for (int i = 0; i < T; ++i) {
             const int j = tid + NT * i;
             u[i] = node_pos(lo, j < p.nx ? j : p.nx - 1, h);
-            qtn[i] = kInf; qtx[i] = -kInf; qin[i] = kInf; qix[i] = -kInf;
+            asm volatile("" : "=v"(qtn[i]), "=v"(qtx[i]), "=v"(qin[i]), "=v"(qix[i]));
         }
         for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
             const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
             if (c0 > 0) stage_chunk<1, NT>(p, row0, c0, cn, sC);
-            for (int s = 0; s < cn; ++s) {
+            int s0 = 0;
+            if (c0 == 0) {
+                const Coef c = sC[0];
+#pragma unroll
+                for (int i = 0; i < T; ++i) {
+                    const double d = u[i] - c.ux;
+                    const double t = c.nk * d;
+                    const double q = fma(t, d, c.a);
+                    const double qi = fma(t, d, c.al);
+                    qtn[i] = q;
+                    qtx[i] = q;
+                    qin[i] = qi;
+                    qix[i] = qi;
+                }
+                s0 = 1;
+            }
+            for (int s = s0; s < cn; ++s) {
                 const Coef c = sC[s];
 #pragma unroll
                 for (int i = 0; i < T; ++i) {
