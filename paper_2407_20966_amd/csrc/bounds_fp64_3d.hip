@@ -74,16 +74,17 @@ void bounds_fp64_3d(BoundsArgs p) {
         const double hz = (box[5] - box[4]) / (double)(p.nz - 1);
 
         for (int z0 = 0; z0 < p.nz; z0 += NZP) {
+            // no +-inf starting values: the stencil's first state sets the
+            // envelopes (the empty asm gives the registers a defined value)
             double qtn[TX][TY][TZ], qtx[TX][TY][TZ], qin[TX][TY][TZ], qix[TX][TY][TZ];
 #pragma unroll
             for (int i = 0; i < TX; ++i)
 #pragma unroll
                 for (int j = 0; j < TY; ++j)
 #pragma unroll
-                    for (int k = 0; k < TZ; ++k) {
-                        qtn[i][j][k] = kInf; qtx[i][j][k] = -kInf;
-                        qin[i][j][k] = kInf; qix[i][j][k] = -kInf;
-                    }
+                    for (int k = 0; k < TZ; ++k)
+                        asm volatile("" : "=v"(qtn[i][j][k]), "=v"(qtx[i][j][k]),
+                                     "=v"(qin[i][j][k]), "=v"(qix[i][j][k]));
 
             for (int64_t c0 = 0; c0 < S; c0 += kMaxStates) {
                 const int cn = (int)((S - c0) < kMaxStates ? (S - c0) : kMaxStates);
@@ -132,10 +133,10 @@ void bounds_fp64_3d(BoundsArgs p) {
                     }
                     for (int s = otid; s < tn; s += NT) sL[s] = sC[t0 + s].al - sC[t0 + s].a;
                     __syncthreads();
-#pragma unroll 2
-                    for (int s = 0; s < tn; ++s) {
-                        double a[TX], zc[TZ], bc[TY][TZ];
-                        const double l = sL[s];
+                    // the x terms, the (y + z) terms and l of state s
+                    auto terms = [&](int s, double* a, double (*bc)[TZ], double& l) {
+                        double zc[TZ];
+                        l = sL[s];
 #pragma unroll
                         for (int i = 0; i < TX; ++i) a[i] = sA[s][tx + BX * i];
 #pragma unroll
@@ -146,6 +147,30 @@ void bounds_fp64_3d(BoundsArgs p) {
 #pragma unroll
                             for (int k = 0; k < TZ; ++k) bc[j][k] = b + zc[k];
                         }
+                    };
+                    int s0 = 0;
+                    if (c0 == 0 && t0 == 0) {
+                        double a[TX], bc[TY][TZ], l;
+                        terms(0, a, bc, l);
+#pragma unroll
+                        for (int i = 0; i < TX; ++i)
+#pragma unroll
+                            for (int j = 0; j < TY; ++j)
+#pragma unroll
+                                for (int k = 0; k < TZ; ++k) {
+                                    const double q = a[i] + bc[j][k];
+                                    const double qi = q + l;
+                                    qtn[i][j][k] = q;
+                                    qtx[i][j][k] = q;
+                                    qin[i][j][k] = qi;
+                                    qix[i][j][k] = qi;
+                                }
+                        s0 = 1;
+                    }
+#pragma unroll 2
+                    for (int s = s0; s < tn; ++s) {
+                        double a[TX], bc[TY][TZ], l;
+                        terms(s, a, bc, l);
 #pragma unroll
                         for (int i = 0; i < TX; ++i)
 #pragma unroll
