@@ -174,8 +174,8 @@ kbl_status kbl_compute_bounds_nodes(const kbl_params* params, int32_t dim, int64
  *                              (0 = one workgroup per element, -k = k
  *                              elements per workgroup)
  * Without either, a 2D launch has each workgroup compute two elements (half
- * as many workgroups as elements; reading (A): one workgroup per element),
- * a 1D or 3D launch one workgroup per element.
+ * as many workgroups as elements), a 1D or 3D launch one workgroup per
+ * element.
  */
 /*
  * kbl_autotune_bounds - picks the launch configuration of kbl_compute_bounds

@@ -75,9 +75,9 @@ kbl_status make_bounds_args(const kbl_params* params, int32_t dim, int64_t n_ele
     a->energy_perstate = (params->flags & KBL_FLAG_ENERGY_PERSTATE) ? 1 : 0;
     // default launch: two elements per workgroup in 2D (the workgroup's
     // set-up, the exp table's staging among it, serves two elements: 1-5%
-    // faster than one per element over the FP64 and mixed tiles), one
-    // workgroup per element otherwise
-    a->grid_blocks = (dim == 2 && !a->energy_perstate) ? -2 : 0;
+    // faster than one per element over the FP64, mixed and per-state
+    // energy tiles), one workgroup per element otherwise
+    a->grid_blocks = dim == 2 ? -2 : 0;
     a->nx = g.n[0];
     a->ny = dim >= 2 ? g.n[1] : 1;
     a->nz = dim == 3 ? g.n[2] : 1;
